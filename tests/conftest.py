@@ -1,0 +1,22 @@
+"""Shared test set-up: repository root on sys.path, the `gpu` marker, and the
+oracle library built on demand (gcc, a few seconds)."""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_built():
+    from oracle import build as ob
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    yield
