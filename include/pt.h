@@ -1,0 +1,195 @@
+/*
+ * pt.h -- C ABI of libpt.so: replica-exchange Metropolis simulation of an
+ * elastic bead-spring homopolymer on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Gross, Janke and Bachmann, "Massively
+ * parallelized replica-exchange simulations of polymers on GPUs" (Comput.
+ * Phys. Commun.; arXiv:1107.3490):
+ *   - model: truncated, shifted Lennard-Jones between all monomer pairs
+ *     (Sec. 3.1, Eqs. 1-2) plus FENE bonds between chain neighbours (Eq. 3);
+ *     total energy Eq. (4);
+ *   - local update: a random monomer is displaced by a vector uniform in a
+ *     cube (Sec. 3.2), accepted with the Metropolis probability (Eq. 5);
+ *   - replica exchange between neighbouring temperatures (Sec. 3.3, Eq. 6);
+ *   - per-sweep energy, end-to-end distance and radius of gyration (the
+ *     kernel description of Sec. 3.4; Eq. 8).
+ *
+ * Arithmetic contract.  Every accept/reject and exchange decision equals,
+ * bit for bit, the one taken by the FP64 reference order:
+ *   r2   = fma(dz, dz, fma(dy, dy, dx*dx))
+ *   e    = 0 if !(r2 < rc^2), else s2 = sig^2/r2, s6 = (s2*s2)*s2,
+ *          e = fma(4 eps, s6*(s6-1), -E_LJ(rc))
+ *   F    = +inf if !(y > 0), else ((-0.5 K) R) R * log(y),
+ *          y = fma(-x, x, 1), x = (sqrt(r2) - r0)/R
+ *   log  = argument reduction to [sqrt(1/2), sqrt(2)), s = f/(2+f), odd
+ *          atanh series to s^21 (Horner, fma), e*ln2 split in two parts
+ *   dE   = (pairwise tree over the zero-padded power-of-two bead range of
+ *          e(new) - e(old), moved bead excluded) + (dF_left + dF_right)
+ *   E    = (tree over rows i of the tree over j of [i<j<N] e(r2_ij))
+ *          + (tree over bonds of F)
+ *   accept move     iff dE <= 0 or beta*dE < -log(u)
+ *   accept exchange iff D >= 0 or log(u) < D, D = (b_i - b_{i+1})(E_i - E_{i+1})
+ * with the derived constants sig^2 = sigma*sigma, rc^2 = r_cut*r_cut,
+ * E_LJ(rc) = (4 eps) * (s6*(s6-1)) at s2 = sig^2/rc^2.  Random numbers are
+ * Philox4x32-10 (Salmon et al., SC'11), key = (seed lo, seed hi):
+ *   move m of sweep t in stream slot g:  counters (m,t,g,0) -> w0..w3 and
+ *   (m,t,g,1) -> v0;  k = floor(w0*N/2^32);  d_a = (((w_a+.5)2^-32)-.5)*edge;
+ *   u = (v0+.5)2^-32;
+ *   exchange of slots (i,i+1) of stream chain c at step e: counter (i,e,c,2).
+ * PT_FP64 evaluates the pair terms in that order.  PT_MIXED evaluates them in
+ * FP32 from FP64 separations, sums in FP64, and re-scores in the FP64 order
+ * every decision that a rigorous error bound cannot settle; its running
+ * energies carry that bound and are re-synchronised with the FP64 energy
+ * whenever an exchange decision needs it.  At the end of a sweep the running
+ * energy is replaced by the FP64-order energy when its bound exceeds 2^-40
+ * (PT_FP64) or 2^-10 (PT_MIXED) of max(1, |E|).
+ *
+ * Threading: a handle is not thread-safe.  Separate handles on separate
+ * streams are independent.  All device work of a handle is enqueued on the
+ * stream given to pt_init.
+ *
+ * Errors: every int-returning call returns PT_OK (0) or a negative code;
+ * pt_last_error() gives a message (thread-local).  Asynchronous device
+ * faults surface as PT_EHIP at the next call that synchronises.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+#define PT_API extern "C" __attribute__((visibility("default")))
+#else
+#define PT_API __attribute__((visibility("default")))
+#endif
+
+enum pt_status {
+    PT_OK = 0,
+    PT_EINVAL = -1,        /* bad argument or model/config value                 */
+    PT_EDOMAIN = -2,       /* an initial bond at or beyond r0 +- R (Eq. 3)       */
+    PT_ENOMEM = -3,        /* workspace smaller than pt_workspace_bytes()        */
+    PT_EHIP = -4,          /* a HIP runtime call failed                          */
+    PT_ESTATE = -5,        /* call not valid in the handle's current state       */
+    PT_EUNSUPPORTED = -6   /* chain longer than the kernels support (N > 2048)   */
+};
+
+enum pt_precision { PT_FP64 = 0, PT_MIXED = 1 };
+
+/* Model parameters (Sec. 3.1; step_edge is the displacement cube edge of
+ * Sec. 3.2, the paper's value being 0.02).  All must be finite and > 0. */
+typedef struct pt_model {
+    double epsilon, sigma, r_cut, fene_k, fene_R, fene_r0, step_edge;
+} pt_model;
+
+/* A batch of independent chains, each with its own temperature ladder.
+ * Host arrays are read during pt_init only (copied). */
+typedef struct pt_config {
+    int32_t n_chains;               /* >= 1                                           */
+    const int32_t *n_beads;         /* [n_chains], 2 <= N <= 2048                      */
+    const int32_t *n_slots;         /* [n_chains], >= 1 (temperatures per chain)       */
+    const double *beta;             /* [sum R_c], finite, >= 0; chain-major            */
+    const double *coords;           /* [sum_c R_c*N_c*3] starting conformation of every
+                                       slot, chain-major, bead-major, xyz (AoS)        */
+    const uint32_t *stream_chain;   /* [n_chains] chain id in exchange counters, or NULL
+                                       (= position in the batch)                       */
+    const uint32_t *stream_slot0;   /* [n_chains] stream id of each chain's slot 0, or
+                                       NULL (= running slot offset)                    */
+    uint64_t seed;                  /* Philox key                                      */
+    int32_t precision;              /* PT_FP64 or PT_MIXED                             */
+    int32_t exchange_every;         /* exchange step after sweep t if (t+1)%k == 0;
+                                       0 = only explicit pt_exchange()                 */
+    int64_t series_capacity;        /* sweeps of (E, Ree^2, Rg^2) per slot kept on the
+                                       device; 0 = none                                */
+    int64_t log_capacity;           /* sweeps of accept bits and exchange outcomes kept
+                                       on the device; 0 = none                         */
+} pt_config;
+
+typedef struct pt_handle pt_handle;
+
+/* Device workspace needed for (model, config), in bytes (256-byte aligned
+ * start required).  Returns 0 and sets the error message on invalid input. */
+PT_API size_t pt_workspace_bytes(const pt_model *model, const pt_config *config);
+
+/* Validate, lay out the caller's device workspace, upload ladders and
+ * coordinates, compute every starting energy in the FP64 order (Eq. 4) and
+ * enqueue all of it on hip_stream (a hipStream_t; NULL = the null stream).
+ * The workspace belongs to the caller, must outlive the handle and must not
+ * be touched while the handle lives.  Synchronises the stream once.
+ * Errors: PT_EINVAL, PT_EDOMAIN, PT_ENOMEM, PT_EUNSUPPORTED, PT_EHIP. */
+PT_API int pt_init(const pt_model *model, const pt_config *config, void *d_workspace,
+                   size_t ws_bytes, void *hip_stream, pt_handle **out);
+
+/* Enqueue n sweeps (Sec. 3.2: one sweep = N attempted single-monomer moves
+ * per slot), each followed by the per-sweep record and, when due, one
+ * exchange step (Sec. 3.3).  Asynchronous.  n >= 0. */
+PT_API int pt_sweep(pt_handle *h, int64_t n_sweeps);
+
+/* Enqueue one exchange step (Eq. 6) now, advancing the exchange index e. */
+PT_API int pt_exchange(pt_handle *h);
+
+/* Synchronous: FP64-order energy E(C) (Eq. 4) of the conformation held by
+ * each slot, [sum R_c] doubles, chain-major. */
+PT_API int pt_energy(pt_handle *h, double *h_energy);
+
+/* Observables and counters.  Every pointer may be NULL.  Synchronous.
+ *   acc     [slots][5]: sweeps recorded, sum E, sum E^2, sum Rg^2, sum Ree^2
+ *           (E is the running energy; Rg^2 per Eq. 8; Ree^2 = |r_N - r_1|^2)
+ *   counts  [slots][7]: moves accepted, exchange attempts of pair (g,g+1),
+ *           exchange accepts of pair (g,g+1), moves re-scored in FP64,
+ *           exchange decisions that needed FP64 energies, moves attempted,
+ *           sweeps that ended with a re-synchronisation of the running energy
+ *   perm    [slots]: conformation held by each slot
+ *   te      [2]: sweeps done t, exchange steps done e */
+PT_API int pt_observables(pt_handle *h, double *acc, int64_t *counts, int32_t *perm, int64_t *te);
+
+/* Zero the observable accumulators (after burn-in).  Asynchronous. */
+PT_API int pt_reset_observables(pt_handle *h);
+
+/* Synchronous copies of the state.
+ *   pt_get_coords:  [sum_c R_c*N_c*3] conformations in their original order
+ *                   (conformation q started in slot q), AoS;
+ *   pt_get_running: running energy and its error bound per conformation. */
+PT_API int pt_get_coords(pt_handle *h, double *h_coords);
+PT_API int pt_get_running(pt_handle *h, double *h_energy, double *h_bound);
+
+/* Synchronous copies of the recorded series and logs (rows since pt_init, at
+ * most the capacities given; older rows are not kept).
+ *   series:     [rows][slots][3] (E, Ree^2, Rg^2) after each sweep, before
+ *               the exchange step;
+ *   accept_log: [rows][words] bit m%64 of word m/64 of a slot's run of
+ *               ceil(N/64) words = move m accepted; slots in order;
+ *   exch_log:   [rows][slots] 1 accepted / 0 rejected for the lower slot of
+ *               each attempted pair, 0xFF otherwise.
+ * *rows receives the number of rows copied. */
+PT_API int pt_get_series(pt_handle *h, double *h_series, int64_t *rows);
+PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_rows,
+                       uint8_t *h_exch_log, int64_t *exch_rows);
+
+/* Timing of the sweep kernels: runs n sweeps like pt_sweep, with HIP events
+ * recorded on the handle's stream around every sweep-kernel launch, then
+ * synchronises.  *sweep_ms = summed sweep-kernel time, *total_ms = wall time
+ * of the whole enqueue on the stream, *launches = sweep-kernel launches. */
+PT_API int pt_time_sweeps(pt_handle *h, int64_t n_sweeps, double *sweep_ms, double *total_ms,
+                          int64_t *launches);
+
+/* Mapping chosen for each chain: beads per lane (a power of two) so that a
+ * 64-lane wavefront covers the chain.  [n_chains]. */
+PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane);
+
+/* Diagnostics of the device arithmetic (used by the test suite).  op:
+ *   0: IEEE sqrt      1: IEEE x/y        2: deterministic log
+ *   3: FENE term of r2 = x                4: LJ term of r2 = x (FP64 order)
+ *   5: FP32 LJ term of r2 from the separation (x, y, 0): out[2i] = value,
+ *      out[2i+1] = its error bound (same bound the mixed path uses)
+ *   6: Philox block: x = counter words (4 per item, as doubles), y[0] = seed
+ *      (as double bit pattern); out[4i..4i+3] = words
+ * Inputs and outputs are host arrays of n items; synchronous; allocates a
+ * temporary device buffer. */
+PT_API int pt_selftest(const pt_model *model, int op, const double *h_x, const double *h_y,
+                       double *h_out, int64_t n);
+
+PT_API void pt_destroy(pt_handle *h);
+PT_API const char *pt_last_error(void);
+
+#endif /* PT_H */

@@ -1,0 +1,79 @@
+// pt_internal.hpp -- structures shared by the host runtime and the kernels of
+// libpt.so (replica-exchange Metropolis for a bead-spring homopolymer,
+// Gross-Janke-Bachmann, arXiv:1107.3490).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pt {
+
+// Model constants as the kernels use them.  The FP64 ones follow the fixed
+// expressions of the public header (Sec. 3.1, Eqs. 1-3); the FP32 ones are
+// their round-to-nearest images for the mixed path.
+struct Consts {
+    double sig2, rc2, four_eps, e_rc, fene_cf, r0, R, edge;
+    float sig2_f, rc2_f, four_eps_f, e_rc_f;
+    // Mixed-path move bound: |S_fp32 - S_exact| <= kbound * sum_j (s6^2 + s6)
+    // over both evaluations of every pair (derivation next to lj32, pt_device.hpp).
+    double kbound;
+    // Largest |E_mod| of an attractive pair, slightly inflated: the LJ terms
+    // that are negative never go below -neg_floor (used by the energy bound).
+    double neg_floor;
+    // A sweep ends with an FP64-order recomputation of the running energy when
+    // its bound exceeds resync_rel * max(1, |E|).
+    double resync_rel;
+};
+
+// Counters per slot (see pt_observables).
+constexpr int PT_NCOUNTS = 7;
+
+// Everything a kernel needs, passed by value.
+struct Tables {
+    // per global slot g
+    const int32_t *slot_chain;   // chain of slot g
+    const int32_t *slot_index;   // position of g inside its chain
+    const uint32_t *slot_gid;    // stream id of slot g (counter word 2 of its moves)
+    const double *beta;          // inverse temperature of slot g
+    int32_t *perm;               // conformation held by slot g
+    double *acc;                 // [g][5] n, sum E, sum E^2, sum Rg^2, sum Ree^2
+    int64_t *counts;             // [g][PT_NCOUNTS] see pt_observables
+    const int64_t *word_off;     // accept-log word offset of slot g
+    // per conformation q (conformation q starts in slot q)
+    double *coords;              // swizzled SoA, bead j at (j mod B) * 64 + j / B
+    const int64_t *coord_off;    // start of conformation q in coords
+    double *e_run;               // running energy
+    double *b_run;               // bound on |e_run - exact sum of the FP64 terms|
+    // per chain c
+    const int32_t *chain_n;      // beads
+    const int32_t *chain_slots;  // slots
+    const int32_t *chain_slot0;  // first global slot
+    const uint32_t *chain_sid;   // stream chain id (exchange counters)
+    // run state: te[0] = sweeps done (t), te[1] = exchange steps done (e)
+    int64_t *te;
+    // optional records
+    uint64_t *accept_log;
+    int64_t log_cap;
+    int64_t words_total;
+    uint8_t *exch_log;
+    double *series;
+    int64_t series_cap;
+    int32_t total_slots;
+    int32_t exchange_every;
+    uint64_t seed;
+    Consts k;
+};
+
+// Kernel launchers (pt_kernels.hip).  bpl = beads per lane of the class,
+// list = global slots (sweep), conformations (energy) or chains (exchange).
+hipError_t launch_sweep(int bpl, bool mixed, const Tables &T, const int32_t *slot_list,
+                        int n_items, hipStream_t s);
+hipError_t launch_energy(int bpl, const Tables &T, const int32_t *conf_list, int n_items,
+                         double *out_e, double *out_b, hipStream_t s);
+hipError_t launch_exchange(int bpl, const Tables &T, const int32_t *chain_list, int n_chains,
+                           int max_pairs, int force, hipStream_t s);
+hipError_t launch_advance(const Tables &T, int force, hipStream_t s);
+hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y,
+                           double *out, int64_t n, hipStream_t s);
+
+}  // namespace pt

@@ -1,0 +1,629 @@
+// pt_runtime.cpp -- host side of libpt.so: validation, workspace layout,
+// uploads, hipGraph replay of sweeps, read-back of state and observables.
+// The C ABI is declared (with its contract) in include/pt.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pt.h"
+#include "pt_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define PT_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(PT_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));             \
+    } while (0)
+
+constexpr int kMaxBeads = 2048;      // 64 lanes x 32 beads per lane
+constexpr double kSentinel = 1.0e30; // x coordinate of padding beads (far from everything)
+
+int beads_per_lane(int n) {
+    int b = 1;
+    while (64 * b < n) b <<= 1;
+    return b;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Offsets of every device array inside the caller's workspace.
+struct Layout {
+    int n_chains = 0, total = 0;
+    std::vector<int> bpl;             // per chain
+    std::vector<int64_t> coord_off;   // per conformation (doubles)
+    std::vector<int64_t> word_off;    // per slot
+    int64_t coord_total = 0, words_total = 0;
+    size_t o_slot_chain, o_slot_index, o_slot_gid, o_beta, o_perm, o_acc, o_counts, o_word_off;
+    size_t o_coord_off, o_e_run, o_b_run, o_coords;
+    size_t o_chain_n, o_chain_slots, o_chain_slot0, o_chain_sid;
+    size_t o_te, o_lists, o_tmp, o_alog, o_elog, o_series;
+    size_t bytes = 0;
+    int64_t log_cap = 0, series_cap = 0;
+    int lists_len = 0;
+};
+
+int validate(const pt_model *m, const pt_config *c) {
+    if (m == nullptr || c == nullptr) return fail(PT_EINVAL, "model and config must be non-NULL");
+    const double v[7] = {m->epsilon, m->sigma, m->r_cut, m->fene_k, m->fene_R, m->fene_r0, m->step_edge};
+    const char *nm[7] = {"epsilon", "sigma", "r_cut", "fene_k", "fene_R", "fene_r0", "step_edge"};
+    for (int i = 0; i < 7; ++i)
+        if (!(isfinite(v[i]) && v[i] > 0.0)) return fail(PT_EINVAL, "model.%s must be finite and > 0", nm[i]);
+    if (!(m->fene_R < m->fene_r0)) return fail(PT_EINVAL, "model.fene_R must be below fene_r0");
+    if (c->n_chains < 1) return fail(PT_EINVAL, "n_chains must be >= 1");
+    if (!c->n_beads || !c->n_slots || !c->beta || !c->coords)
+        return fail(PT_EINVAL, "n_beads, n_slots, beta and coords must be non-NULL");
+    if (c->precision != PT_FP64 && c->precision != PT_MIXED) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_MIXED");
+    if (c->exchange_every < 0) return fail(PT_EINVAL, "exchange_every must be >= 0");
+    if (c->series_capacity < 0 || c->log_capacity < 0) return fail(PT_EINVAL, "capacities must be >= 0");
+    int64_t total = 0;
+    for (int ch = 0; ch < c->n_chains; ++ch) {
+        if (c->n_beads[ch] < 2) return fail(PT_EINVAL, "chain %d: n_beads must be >= 2", ch);
+        if (c->n_beads[ch] > kMaxBeads) return fail(PT_EUNSUPPORTED, "chain %d: %d beads exceeds %d", ch, c->n_beads[ch], kMaxBeads);
+        if (c->n_slots[ch] < 1) return fail(PT_EINVAL, "chain %d: n_slots must be >= 1", ch);
+        total += c->n_slots[ch];
+    }
+    if (total > (1 << 24)) return fail(PT_EUNSUPPORTED, "too many slots (%lld)", (long long)total);
+    for (int64_t g = 0; g < total; ++g)
+        if (!(isfinite(c->beta[g]) && c->beta[g] >= 0.0)) return fail(PT_EINVAL, "beta[%lld] must be finite and >= 0", (long long)g);
+    return PT_OK;
+}
+
+// Constants in the fixed expressions of include/pt.h, plus the mixed-path bound.
+pt::Consts make_consts(const pt_model *m, bool mixed) {
+    pt::Consts k;
+    k.sig2 = m->sigma * m->sigma;
+    k.rc2 = m->r_cut * m->r_cut;
+    k.four_eps = 4.0 * m->epsilon;
+    {
+        const double s2 = k.sig2 / k.rc2;
+        const double s6 = (s2 * s2) * s2;
+        k.e_rc = k.four_eps * (s6 * (s6 - 1.0));
+    }
+    k.fene_cf = ((-0.5 * m->fene_k) * m->fene_R) * m->fene_R;
+    k.r0 = m->fene_r0;
+    k.R = m->fene_R;
+    k.edge = m->step_edge;
+    k.sig2_f = (float)k.sig2;
+    k.rc2_f = (float)k.rc2;
+    k.four_eps_f = (float)k.four_eps;
+    k.e_rc_f = (float)k.e_rc;
+    // kappa of the FP32 term bound (derivation next to lj32 in pt_device.hpp).
+    const double s2c = k.sig2 / k.rc2;
+    const double s6c = s2c * s2c * s2c;
+    const double brc = s6c * (1.0 + s6c);
+    const double c_erc = 3.0 * fabs(k.e_rc) / (k.four_eps * brc);
+    const double slope = (3.0 * k.four_eps / k.rc2) * fabs(2.0 * s6c * s6c - s6c);  // |dE/dr^2| at rc
+    const double c_win = slope * 6.0 * k.rc2 * (1.0 + 0x1p-4) / (k.four_eps * brc);
+    const double kappa = std::max(128.0, ceil(1.25 * (62.0 + c_erc + c_win)));
+    k.kbound = kappa * 0x1p-24 * k.four_eps * (1.0 + 0x1p-8);
+    k.neg_floor = (m->epsilon + fabs(k.e_rc)) * (1.0 + 0x1p-30);
+    k.resync_rel = mixed ? 0x1p-10 : 0x1p-40;
+    return k;
+}
+
+Layout plan(const pt_config *c) {
+    Layout L;
+    L.n_chains = c->n_chains;
+    int64_t total = 0;
+    for (int ch = 0; ch < c->n_chains; ++ch) total += c->n_slots[ch];
+    L.total = (int)total;
+    L.bpl.resize(c->n_chains);
+    L.coord_off.resize(total);
+    L.word_off.resize(total);
+    int g = 0;
+    for (int ch = 0; ch < c->n_chains; ++ch) {
+        L.bpl[ch] = beads_per_lane(c->n_beads[ch]);
+        for (int s = 0; s < c->n_slots[ch]; ++s, ++g) {
+            L.coord_off[g] = L.coord_total;
+            L.word_off[g] = L.words_total;
+            L.coord_total += 3 * 64 * L.bpl[ch];
+            L.words_total += (c->n_beads[ch] + 63) / 64;
+        }
+    }
+    L.log_cap = c->log_capacity;
+    L.series_cap = c->series_capacity;
+    // lists: per class slot lists (total) + chain lists (n_chains)
+    L.lists_len = L.total + L.n_chains;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    const size_t S = (size_t)L.total, C = (size_t)L.n_chains;
+    L.o_slot_chain = take(4 * S);
+    L.o_slot_index = take(4 * S);
+    L.o_slot_gid = take(4 * S);
+    L.o_beta = take(8 * S);
+    L.o_perm = take(4 * S);
+    L.o_acc = take(8 * 5 * S);
+    L.o_counts = take(8 * pt::PT_NCOUNTS * S);
+    L.o_word_off = take(8 * S);
+    L.o_coord_off = take(8 * S);
+    L.o_e_run = take(8 * S);
+    L.o_b_run = take(8 * S);
+    L.o_coords = take(8 * (size_t)L.coord_total);
+    L.o_chain_n = take(4 * C);
+    L.o_chain_slots = take(4 * C);
+    L.o_chain_slot0 = take(4 * C);
+    L.o_chain_sid = take(4 * C);
+    L.o_te = take(16);
+    L.o_lists = take(4 * (size_t)L.lists_len);
+    L.o_tmp = take(8 * S);
+    L.o_alog = take(8 * (size_t)L.words_total * (size_t)L.log_cap);
+    L.o_elog = take(S * (size_t)L.log_cap);
+    L.o_series = take(8 * 3 * S * (size_t)L.series_cap);
+    L.bytes = o;
+    return L;
+}
+
+// Same expression as the kernels' FENE argument (r^2 -> y); used for the
+// domain check of the starting bonds.
+double fene_y(const pt::Consts &k, const double *a, const double *b) {
+    const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double x = (sqrt(r2) - k.r0) / k.R;
+    return fma(-x, x, 1.0);
+}
+
+}  // namespace
+
+struct Class {
+    int bpl = 0;
+    int n_slots = 0, n_chains = 0, max_pairs = 0;
+    int32_t *d_slots = nullptr;   // slot (= starting conformation) list
+    int32_t *d_chains = nullptr;  // chain list
+};
+
+struct pt_handle {
+    pt_model model;
+    pt::Consts k;
+    Layout L;
+    pt::Tables T;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    char *ws = nullptr;
+    bool mixed = false;
+    std::vector<Class> classes;
+    std::vector<int32_t> n_beads, n_slots;
+    int exchange_every = 1;
+    int64_t t_host = 0, e_host = 0;  // counters as enqueued
+    hipGraphExec_t graph1 = nullptr, graph16 = nullptr;
+    double *d_tmp = nullptr;
+};
+
+namespace {
+
+int enqueue_sweep(pt_handle *h, hipStream_t s) {
+    for (const Class &c : h->classes) {
+        hipError_t e = pt::launch_sweep(c.bpl, h->mixed, h->T, c.d_slots, c.n_slots, s);
+        if (e != hipSuccess) return fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
+    }
+    for (const Class &c : h->classes) {
+        hipError_t e = pt::launch_exchange(c.bpl, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, s);
+        if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = pt::launch_advance(h->T, 0, s);
+    if (e != hipSuccess) return fail(PT_EHIP, "advance launch failed: %s", hipGetErrorString(e));
+    return PT_OK;
+}
+
+int capture(pt_handle *h, int sweeps, hipGraphExec_t *out) {
+    hipGraph_t graph = nullptr;
+    PT_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = PT_OK;
+    for (int i = 0; i < sweeps && rc == PT_OK; ++i) rc = enqueue_sweep(h, h->cap_stream);
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+    if (rc != PT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(PT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return PT_OK;
+}
+
+void advance_host(pt_handle *h, int64_t sweeps) {
+    for (int64_t i = 0; i < sweeps; ++i) {
+        if (h->exchange_every > 0 && (h->t_host + 1) % h->exchange_every == 0) h->e_host += 1;
+        h->t_host += 1;
+    }
+}
+
+}  // namespace
+
+PT_API size_t pt_workspace_bytes(const pt_model *model, const pt_config *config) {
+    if (validate(model, config) != PT_OK) return 0;
+    return plan(config).bytes;
+}
+
+PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspace, size_t ws_bytes,
+                   void *hip_stream, pt_handle **out) {
+    if (out == nullptr) return fail(PT_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    int rc = validate(model, cfg);
+    if (rc != PT_OK) return rc;
+    Layout L = plan(cfg);
+    if (d_workspace == nullptr || ws_bytes < L.bytes)
+        return fail(PT_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.bytes);
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+    const pt::Consts k = make_consts(model, cfg->precision == PT_MIXED);
+
+    // Host-side checks and swizzled coordinates.
+    const int S = L.total, C = L.n_chains;
+    std::vector<int32_t> slot_chain(S), slot_index(S), perm(S);
+    std::vector<uint32_t> slot_gid(S), chain_sid(C);
+    std::vector<int32_t> chain_n(C), chain_slots(C), chain_slot0(C);
+    std::vector<double> coords((size_t)L.coord_total);
+    {
+        int g = 0;
+        int64_t src = 0;
+        for (int ch = 0; ch < C; ++ch) {
+            const int n = cfg->n_beads[ch], B = L.bpl[ch], NP = 64 * B;
+            chain_n[ch] = n;
+            chain_slots[ch] = cfg->n_slots[ch];
+            chain_slot0[ch] = g;
+            chain_sid[ch] = cfg->stream_chain ? cfg->stream_chain[ch] : (uint32_t)ch;
+            const uint32_t sid0 = cfg->stream_slot0 ? cfg->stream_slot0[ch] : (uint32_t)g;
+            for (int s = 0; s < cfg->n_slots[ch]; ++s, ++g) {
+                slot_chain[g] = ch;
+                slot_index[g] = s;
+                slot_gid[g] = sid0 + (uint32_t)s;
+                perm[g] = g;
+                const double *xyz = cfg->coords + src;
+                for (int j = 0; j < 3 * n; ++j)
+                    if (!isfinite(xyz[j])) return fail(PT_EINVAL, "slot %d: non-finite coordinate", g);
+                for (int j = 0; j + 1 < n; ++j)
+                    if (!(fene_y(k, xyz + 3 * j, xyz + 3 * (j + 1)) > 0.0))
+                        return fail(PT_EDOMAIN, "slot %d: bond (%d,%d) at or beyond r0 +- R", g, j, j + 1);
+                double *dst = coords.data() + L.coord_off[g];
+                for (int j = 0; j < NP; ++j) {
+                    const int p = ((j & (B - 1)) * 64) + j / B;
+                    dst[p] = (j < n) ? xyz[3 * j] : kSentinel;
+                    dst[NP + p] = (j < n) ? xyz[3 * j + 1] : 0.0;
+                    dst[2 * NP + p] = (j < n) ? xyz[3 * j + 2] : 0.0;
+                }
+                src += 3 * (int64_t)n;
+            }
+        }
+    }
+
+    pt_handle *h = new (std::nothrow) pt_handle();
+    if (h == nullptr) return fail(PT_ENOMEM, "host allocation failed");
+    h->model = *model;
+    h->k = k;
+    h->L = L;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char *)d_workspace;
+    h->mixed = cfg->precision == PT_MIXED;
+    h->exchange_every = cfg->exchange_every;
+    h->n_beads.assign(cfg->n_beads, cfg->n_beads + C);
+    h->n_slots.assign(cfg->n_slots, cfg->n_slots + C);
+    char *w = h->ws;
+    pt::Tables &T = h->T;
+    T.slot_chain = (const int32_t *)(w + L.o_slot_chain);
+    T.slot_index = (const int32_t *)(w + L.o_slot_index);
+    T.slot_gid = (const uint32_t *)(w + L.o_slot_gid);
+    T.beta = (const double *)(w + L.o_beta);
+    T.perm = (int32_t *)(w + L.o_perm);
+    T.acc = (double *)(w + L.o_acc);
+    T.counts = (int64_t *)(w + L.o_counts);
+    T.word_off = (const int64_t *)(w + L.o_word_off);
+    T.coords = (double *)(w + L.o_coords);
+    T.coord_off = (const int64_t *)(w + L.o_coord_off);
+    T.e_run = (double *)(w + L.o_e_run);
+    T.b_run = (double *)(w + L.o_b_run);
+    T.chain_n = (const int32_t *)(w + L.o_chain_n);
+    T.chain_slots = (const int32_t *)(w + L.o_chain_slots);
+    T.chain_slot0 = (const int32_t *)(w + L.o_chain_slot0);
+    T.chain_sid = (const uint32_t *)(w + L.o_chain_sid);
+    T.te = (int64_t *)(w + L.o_te);
+    T.accept_log = L.log_cap > 0 ? (uint64_t *)(w + L.o_alog) : nullptr;
+    T.log_cap = L.log_cap;
+    T.words_total = L.words_total;
+    T.exch_log = L.log_cap > 0 ? (uint8_t *)(w + L.o_elog) : nullptr;
+    T.series = L.series_cap > 0 ? (double *)(w + L.o_series) : nullptr;
+    T.series_cap = L.series_cap;
+    T.total_slots = S;
+    T.exchange_every = cfg->exchange_every;
+    T.seed = cfg->seed;
+    T.k = k;
+    h->d_tmp = (double *)(w + L.o_tmp);
+
+    // Classes by beads per lane.
+    std::map<int, std::vector<int>> cls_chains;
+    for (int ch = 0; ch < C; ++ch) cls_chains[L.bpl[ch]].push_back(ch);
+    std::vector<int32_t> lists;
+    lists.reserve(L.lists_len);
+    for (auto &kv : cls_chains) {
+        Class cl;
+        cl.bpl = kv.first;
+        const size_t slot_at = lists.size();
+        for (int ch : kv.second)
+            for (int s = 0; s < cfg->n_slots[ch]; ++s) lists.push_back(chain_slot0[ch] + s);
+        cl.n_slots = (int)(lists.size() - slot_at);
+        const size_t chain_at = lists.size();
+        for (int ch : kv.second) {
+            lists.push_back(ch);
+            cl.max_pairs = std::max(cl.max_pairs, cfg->n_slots[ch] / 2);
+        }
+        cl.n_chains = (int)kv.second.size();
+        cl.d_slots = (int32_t *)(w + L.o_lists) + slot_at;
+        cl.d_chains = (int32_t *)(w + L.o_lists) + chain_at;
+        h->classes.push_back(cl);
+    }
+
+    auto fin = [&](int code) {
+        if (code != PT_OK) pt_destroy(h);
+        return code;
+    };
+    std::vector<int64_t> te = {0, 0};
+#define PT_UP(off, vec) \
+    if (!(vec).empty()) { \
+        hipError_t e_ = hipMemcpyAsync(w + (off), (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice, h->stream); \
+        if (e_ != hipSuccess) return fin(fail(PT_EHIP, "upload failed: %s", hipGetErrorString(e_))); }
+    std::vector<double> beta(cfg->beta, cfg->beta + S);
+    PT_UP(L.o_slot_chain, slot_chain);
+    PT_UP(L.o_slot_index, slot_index);
+    PT_UP(L.o_slot_gid, slot_gid);
+    PT_UP(L.o_beta, beta);
+    PT_UP(L.o_perm, perm);
+    PT_UP(L.o_word_off, L.word_off);
+    PT_UP(L.o_coord_off, L.coord_off);
+    PT_UP(L.o_coords, coords);
+    PT_UP(L.o_chain_n, chain_n);
+    PT_UP(L.o_chain_slots, chain_slots);
+    PT_UP(L.o_chain_slot0, chain_slot0);
+    PT_UP(L.o_chain_sid, chain_sid);
+    PT_UP(L.o_te, te);
+    PT_UP(L.o_lists, lists);
+#undef PT_UP
+    hipError_t e = hipMemsetAsync(w + L.o_acc, 0, 8 * 5 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_counts, 0, 8 * pt::PT_NCOUNTS * (size_t)S, h->stream);
+    if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_elog, 0xFF, (size_t)S * L.log_cap, h->stream);
+    if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_alog, 0, 8 * (size_t)L.words_total * L.log_cap, h->stream);
+    if (e != hipSuccess) return fin(fail(PT_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e)));
+    // Starting energies in the FP64 order; their bounds seed the running bounds.
+    for (const Class &cl : h->classes) {
+        e = pt::launch_energy(cl.bpl, T, cl.d_slots, cl.n_slots, T.e_run, T.b_run, h->stream);
+        if (e != hipSuccess) return fin(fail(PT_EHIP, "energy launch failed: %s", hipGetErrorString(e)));
+    }
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fin(fail(PT_EHIP, "initialisation failed: %s", hipGetErrorString(e)));
+    e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fin(fail(PT_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)));
+    *out = h;
+    return PT_OK;
+}
+
+PT_API int pt_sweep(pt_handle *h, int64_t n) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
+    if (n == 0) return PT_OK;
+    if (n >= 16 && h->graph16 == nullptr) {
+        int rc = capture(h, 16, &h->graph16);
+        if (rc != PT_OK) return rc;
+    }
+    if (h->graph1 == nullptr) {
+        int rc = capture(h, 1, &h->graph1);
+        if (rc != PT_OK) return rc;
+    }
+    int64_t left = n;
+    while (left >= 16) {
+        PT_HIP(hipGraphLaunch(h->graph16, h->stream));
+        left -= 16;
+    }
+    while (left > 0) {
+        PT_HIP(hipGraphLaunch(h->graph1, h->stream));
+        left -= 1;
+    }
+    advance_host(h, n);
+    return PT_OK;
+}
+
+PT_API int pt_exchange(pt_handle *h) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    for (const Class &c : h->classes) {
+        hipError_t e = pt::launch_exchange(c.bpl, h->T, c.d_chains, c.n_chains, c.max_pairs, 1, h->stream);
+        if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = pt::launch_advance(h->T, 1, h->stream);
+    if (e != hipSuccess) return fail(PT_EHIP, "advance launch failed: %s", hipGetErrorString(e));
+    h->e_host += 1;
+    return PT_OK;
+}
+
+PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *total_ms, int64_t *launches) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
+    const size_t nev = (size_t)n * h->classes.size();
+    std::vector<hipEvent_t> ev(2 * nev + 2, nullptr);
+    for (auto &x : ev) PT_HIP(hipEventCreate(&x));
+    int rc = PT_OK;
+    PT_HIP(hipEventRecord(ev[2 * nev], h->stream));
+    size_t k = 0;
+    for (int64_t i = 0; i < n && rc == PT_OK; ++i) {
+        for (const Class &c : h->classes) {
+            PT_HIP(hipEventRecord(ev[2 * k], h->stream));
+            hipError_t e = pt::launch_sweep(c.bpl, h->mixed, h->T, c.d_slots, c.n_slots, h->stream);
+            if (e != hipSuccess) { rc = fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e)); break; }
+            PT_HIP(hipEventRecord(ev[2 * k + 1], h->stream));
+            ++k;
+        }
+        for (const Class &c : h->classes) {
+            hipError_t e = pt::launch_exchange(c.bpl, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, h->stream);
+            if (e != hipSuccess) { rc = fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e)); break; }
+        }
+        if (rc == PT_OK) {
+            hipError_t e = pt::launch_advance(h->T, 0, h->stream);
+            if (e != hipSuccess) rc = fail(PT_EHIP, "advance launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    PT_HIP(hipEventRecord(ev[2 * nev + 1], h->stream));
+    PT_HIP(hipEventSynchronize(ev[2 * nev + 1]));
+    if (rc == PT_OK) {
+        double acc = 0.0;
+        for (size_t i = 0; i < k; ++i) {
+            float ms = 0.f;
+            PT_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+            acc += ms;
+        }
+        float tot = 0.f;
+        PT_HIP(hipEventElapsedTime(&tot, ev[2 * nev], ev[2 * nev + 1]));
+        if (sweep_ms) *sweep_ms = acc;
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = (int64_t)k;
+        advance_host(h, n);
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    return rc;
+}
+
+PT_API int pt_energy(pt_handle *h, double *h_e) {
+    if (h == nullptr || h_e == nullptr) return fail(PT_EINVAL, "NULL argument");
+    for (const Class &c : h->classes) {
+        hipError_t e = pt::launch_energy(c.bpl, h->T, c.d_slots, c.n_slots, h->d_tmp, nullptr, h->stream);
+        if (e != hipSuccess) return fail(PT_EHIP, "energy launch failed: %s", hipGetErrorString(e));
+    }
+    PT_HIP(hipMemcpyAsync(h_e, h->d_tmp, 8 * (size_t)h->L.total, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_observables(pt_handle *h, double *acc, int64_t *counts, int32_t *perm, int64_t *te) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    const size_t S = (size_t)h->L.total;
+    if (acc) PT_HIP(hipMemcpyAsync(acc, h->ws + h->L.o_acc, 8 * 5 * S, hipMemcpyDeviceToHost, h->stream));
+    if (counts) PT_HIP(hipMemcpyAsync(counts, h->ws + h->L.o_counts, 8 * pt::PT_NCOUNTS * S, hipMemcpyDeviceToHost, h->stream));
+    if (perm) PT_HIP(hipMemcpyAsync(perm, h->ws + h->L.o_perm, 4 * S, hipMemcpyDeviceToHost, h->stream));
+    if (te) PT_HIP(hipMemcpyAsync(te, h->ws + h->L.o_te, 16, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_reset_observables(pt_handle *h) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    PT_HIP(hipMemsetAsync(h->ws + h->L.o_acc, 0, 8 * 5 * (size_t)h->L.total, h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_get_coords(pt_handle *h, double *out) {
+    if (h == nullptr || out == nullptr) return fail(PT_EINVAL, "NULL argument");
+    std::vector<double> sw((size_t)h->L.coord_total);
+    PT_HIP(hipMemcpyAsync(sw.data(), h->ws + h->L.o_coords, 8 * sw.size(), hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    int g = 0;
+    int64_t dst = 0;
+    for (int ch = 0; ch < h->L.n_chains; ++ch) {
+        const int n = h->n_beads[ch], B = h->L.bpl[ch], NP = 64 * B;
+        for (int s = 0; s < h->n_slots[ch]; ++s, ++g) {
+            const double *src = sw.data() + h->L.coord_off[g];
+            for (int j = 0; j < n; ++j) {
+                const int p = ((j & (B - 1)) * 64) + j / B;
+                out[dst + 3 * j] = src[p];
+                out[dst + 3 * j + 1] = src[NP + p];
+                out[dst + 3 * j + 2] = src[2 * NP + p];
+            }
+            dst += 3 * (int64_t)n;
+        }
+    }
+    return PT_OK;
+}
+
+PT_API int pt_get_running(pt_handle *h, double *he, double *hb) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    const size_t S = (size_t)h->L.total;
+    if (he) PT_HIP(hipMemcpyAsync(he, h->ws + h->L.o_e_run, 8 * S, hipMemcpyDeviceToHost, h->stream));
+    if (hb) PT_HIP(hipMemcpyAsync(hb, h->ws + h->L.o_b_run, 8 * S, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_get_series(pt_handle *h, double *out, int64_t *rows) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    const int64_t r = std::min<int64_t>(h->t_host, h->L.series_cap);
+    if (rows) *rows = r;
+    if (out && r > 0)
+        PT_HIP(hipMemcpyAsync(out, h->ws + h->L.o_series, 8 * 3 * (size_t)h->L.total * r, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_get_logs(pt_handle *h, uint64_t *alog, int64_t *arows, uint8_t *elog, int64_t *erows) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    const int64_t ra = std::min<int64_t>(h->t_host, h->L.log_cap);
+    const int64_t re = std::min<int64_t>(h->e_host, h->L.log_cap);
+    if (arows) *arows = ra;
+    if (erows) *erows = re;
+    if (alog && ra > 0)
+        PT_HIP(hipMemcpyAsync(alog, h->ws + h->L.o_alog, 8 * (size_t)h->L.words_total * ra, hipMemcpyDeviceToHost, h->stream));
+    if (elog && re > 0)
+        PT_HIP(hipMemcpyAsync(elog, h->ws + h->L.o_elog, (size_t)h->L.total * re, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl) {
+    if (h == nullptr || bpl == nullptr) return fail(PT_EINVAL, "NULL argument");
+    for (int c = 0; c < h->L.n_chains; ++c) bpl[c] = h->L.bpl[c];
+    return PT_OK;
+}
+
+PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const double *hy, double *hout, int64_t n) {
+    if (model == nullptr || hx == nullptr || hout == nullptr || n < 0) return fail(PT_EINVAL, "bad argument");
+    if (op < 0 || op > 6) return fail(PT_EINVAL, "unknown op %d", op);
+    if (n == 0) return PT_OK;
+    const pt::Consts k = make_consts(model, true);
+    const size_t nin = (op == 6) ? 4 * (size_t)n : (size_t)n;
+    const size_t ny = (op == 6) ? 2 : (size_t)n;
+    const size_t nout = (op == 5) ? 2 * (size_t)n : (op == 6) ? 4 * (size_t)n : (size_t)n;
+    double *dx = nullptr, *dy = nullptr, *dout = nullptr;
+    std::vector<double> zeros;
+    if (hy == nullptr) {
+        zeros.assign(ny, 0.0);
+        hy = zeros.data();
+    }
+    PT_HIP(hipMalloc(&dx, 8 * nin));
+    hipError_t e = hipMalloc(&dy, 8 * ny);
+    if (e == hipSuccess) e = hipMalloc(&dout, 8 * nout);
+    if (e == hipSuccess) e = hipMemcpy(dx, hx, 8 * nin, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dy, hy, 8 * ny, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = pt::launch_selftest(k, op, dx, dy, dout, n, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(hout, dout, 8 * nout, hipMemcpyDeviceToHost);
+    (void)hipFree(dx);
+    (void)hipFree(dy);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(PT_EHIP, "selftest failed: %s", hipGetErrorString(e));
+    return PT_OK;
+}
+
+PT_API void pt_destroy(pt_handle *h) {
+    if (h == nullptr) return;
+    if (h->graph1) (void)hipGraphExecDestroy(h->graph1);
+    if (h->graph16) (void)hipGraphExecDestroy(h->graph16);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+}
+
+PT_API const char *pt_last_error(void) { return g_err.c_str(); }

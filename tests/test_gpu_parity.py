@@ -1,0 +1,206 @@
+"""GPU parity of libpt.so against the CPU oracle.
+
+The contract (include/pt.h): accept/reject and exchange decisions are
+bit-identical to the oracle's on the same Philox streams, so coordinates,
+slot permutations and the FP64-order energies (pt_energy) are bit-identical
+too; the running energies the kernels carry stay within their own rigorous
+bound of the FP64-order energy, and for the plain FP64 path within 1e-9
+relative of it.  Every case runs the oracle on the same seeded inputs.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1107_3490_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1107_3490_amd import pt
+    pt.lib()  # raises if the HIP library is missing: no fallback
+    yield
+
+
+def _pt():
+    from paper_1107_3490_amd import pt
+    return pt
+
+
+def run_both(w, sweeps, precision, label):
+    pt = _pt()
+    print(f"\n[case] {label}: chains={len(w.n_beads)} N={sorted(set(w.n_beads))} "
+          f"slots={w.total_slots} sweeps={sweeps} precision={precision}", flush=True)
+    sim = pt.Simulation(w, precision=precision, series_capacity=sweeps, log_capacity=sweeps)
+    sim.sweep(sweeps)
+    g = dict(coords=sim.coords(), energy=sim.energy(), obs=sim.observables(), series=sim.series())
+    g["alog"], g["elog"] = sim.logs()
+    g["e_run"], g["b_run"] = sim.running()
+    sim.close()
+    orc = O.Simulation(w)
+    r = orc.run(sweeps, accept_log=True, exch_log=True, series=True)
+    o = dict(coords=orc.coords, energy=orc.energy, perm=orc.perm, alog=r["accept_log"],
+             elog=r["exch_log"], series=r["series"], accepts=orc.accepts,
+             exch_accepts=orc.exch_accepts, exch_tries=orc.exch_tries)
+    return g, o
+
+
+def assert_parity(g, o, precision):
+    # decisions: bit-identical logs
+    assert g["alog"].shape == o["alog"].shape
+    bad = np.argwhere(g["alog"] != o["alog"])
+    assert bad.size == 0, f"accept logs differ first at (sweep, word) {bad[0]}"
+    assert np.array_equal(g["elog"], o["elog"]), "exchange logs differ"
+    assert np.array_equal(g["obs"]["perm"], o["perm"])
+    assert np.array_equal(g["obs"]["counts"][:, 0], o["accepts"])
+    assert np.array_equal(g["obs"]["counts"][:, 1], o["exch_tries"])
+    assert np.array_equal(g["obs"]["counts"][:, 2], o["exch_accepts"])
+    # state: bit-identical coordinates and FP64-order energies
+    assert np.array_equal(g["coords"], o["coords"])
+    assert np.array_equal(g["energy"], o["energy"])
+    # per-sweep shape observables are FP64-order trees: bit-identical
+    assert np.array_equal(g["series"][:, :, 1:], o["series"][:, :, 1:])
+    # running energies: within their rigorous bound of the FP64-order energy
+    perm = g["obs"]["perm"]
+    e_slot, b_slot = g["e_run"][perm], g["b_run"][perm]
+    err = np.abs(e_slot - o["energy"])
+    assert np.all(err <= b_slot * (1 + 1e-6) + 1e-300), (err, b_slot)
+    ser_err = np.abs(g["series"][:, :, 0] - o["series"][:, :, 0])
+    rel = ser_err / np.maximum(1.0, np.abs(o["series"][:, :, 0]))
+    print(f"  running-energy error vs FP64 order: max abs {ser_err.max():.3e}, "
+          f"max rel {rel.max():.3e}; rescored moves {int(g['obs']['counts'][:, 3].sum())} of "
+          f"{int(g['obs']['counts'][:, 5].sum())}; exchange recomputes {int(g['obs']['counts'][:, 4].sum())}",
+          flush=True)
+    if precision == "fp64":
+        assert rel.max() <= 1e-9
+
+
+def test_device_arithmetic_matches_host():
+    pt = _pt()
+    m = I.model_params()
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.random(200000) * 4, np.exp(rng.uniform(-700, 700, 100000)),
+                        [0.0, 1.0, 2.0, 0.25, 5e-324, 1e-310, 1e300]])
+    assert np.array_equal(pt.pt_selftest(m, pt.OP_SQRT, x), np.sqrt(x)), "FP64 sqrt not IEEE"
+    y = np.exp(rng.uniform(-300, 300, x.size))
+    x, y = x[np.isfinite(x / y)], y[np.isfinite(x / y)]
+    assert np.array_equal(pt.pt_selftest(m, pt.OP_DIV, x, y), x / y), "FP64 division not IEEE"
+    xs = np.concatenate([rng.random(20000), 1 - rng.random(5000) * 1e-3, np.exp(rng.uniform(-700, 700, 5000))])
+    got = pt.pt_selftest(m, pt.OP_LOG, xs)
+    want = np.array([O.plog(v) for v in xs])
+    assert np.array_equal(got, want), "device log differs from the oracle's"
+    r2 = np.concatenate([rng.uniform(0.1, 3.0, 20000), rng.uniform(0.16, 1.0, 20000),
+                         [0.49, 0.36, 0.64, m["r_cut"] ** 2, 0.0]])
+    c = O.consts(m)
+    assert np.array_equal(pt.pt_selftest(m, pt.OP_LJ, r2), np.array([O.lib().orc_lj(c, v) for v in r2]))
+    assert np.array_equal(pt.pt_selftest(m, pt.OP_FENE, r2), np.array([O.lib().orc_fene(c, v) for v in r2]))
+    ctr = rng.integers(0, 2 ** 32, size=(4000, 4)).astype(np.float64)
+    seed = 0x0123456789ABCDEF
+    out = pt.pt_selftest(m, pt.OP_PHILOX, ctr.ravel(), [seed & 0xFFFFFFFF, seed >> 32]).reshape(-1, 4)
+    want = np.array([O.philox([int(v) for v in row], seed) for row in ctr], dtype=np.float64)
+    assert np.array_equal(out, want)
+
+
+def test_fp32_term_bound_is_sound():
+    """The per-term error bound the mixed path relies on, on random pair geometries
+    (near contact, around the minimum, around the cutoff, far)."""
+    pt = _pt()
+    m = I.model_params()
+    rng = np.random.default_rng(1)
+    rc = m["r_cut"]
+    r = np.concatenate([rng.uniform(0.3, 3.0, 300000), rc * (1 + rng.uniform(-1e-6, 1e-6, 100000)),
+                        rng.uniform(0.05, 0.5, 50000), rng.uniform(0.69, 0.71, 50000)])
+    phi = rng.uniform(0, 2 * math.pi, r.size)
+    dx, dy = r * np.cos(phi), r * np.sin(phi)
+    out = pt.pt_selftest(m, pt.OP_LJ32, dx, dy).reshape(-1, 2)
+    # Reference: Eqs. (1)-(2) in 64-bit-mantissa long double from the exact
+    # FP64 separation (error ~1e-19 relative, far below the bounds checked).
+    L = np.longdouble
+    r2 = dx.astype(L) ** 2 + dy.astype(L) ** 2
+    s6 = (L(m["sigma"]) ** 2 / r2) ** 3
+    s6c = (L(m["sigma"]) ** 2 / L(m["r_cut"]) ** 2) ** 3
+    exact = np.where(r2 < L(m["r_cut"]) ** 2, 4 * (s6 * s6 - s6) - 4 * (s6c * s6c - s6c), L(0))
+    err = np.abs(out[:, 0].astype(L) - exact).astype(np.float64)
+    ratio = np.max(err / np.maximum(out[:, 1], 1e-300))
+    print(f"\n  FP32 term: max observed/bound = {ratio:.3f}", flush=True)
+    assert np.all(err <= out[:, 1])
+    assert ratio <= 0.5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_full_run(precision):
+    w = I.named("c1")
+    g, o = run_both(w, w.sweeps, precision, "c1 full")
+    assert_parity(g, o, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c2_reduced(precision):
+    w = I.named("c2")
+    g, o = run_both(w, 300, precision, "c2 300 sweeps")
+    assert_parity(g, o, precision)
+
+
+def test_c3_reduced_mixed():
+    w = I.named("c3")
+    g, o = run_both(w, 12, "mixed", "c3 12 sweeps")
+    assert_parity(g, o, "mixed")
+
+
+def test_c4_batched_uneven_reduced():
+    w = I.named("c4")
+    g, o = run_both(w, 6, "mixed", "c4 6 sweeps")
+    assert_parity(g, o, "mixed")
+
+
+def test_c5_chain_subset_full_size():
+    """Full-size chains (N = 2000) of the large workload, one chain's ladder cut
+    to 32 slots, same streams as in the full batch."""
+    w = I.subset(I.named("c5"), [3], slots=32)
+    g, o = run_both(w, 2, "mixed", "c5 chain 3, 32 slots, 2 sweeps")
+    assert_parity(g, o, "mixed")
+
+
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 129])
+def test_edge_lengths(n):
+    w = I.make_workload([n], [5], [(0.2, 2.0)], "walk", 40 + n, 0, "fp64")
+    for prec in ("fp64", "mixed"):
+        g, o = run_both(w, 25, prec, f"N={n}")
+        assert_parity(g, o, prec)
+
+
+def test_single_slot_and_no_exchange():
+    w = I.make_workload([40, 17], [1, 3], [(0.5, 0.5), (0.3, 1.0)], "walk", 77, 0, "fp64",
+                        exchange_every=0)
+    g, o = run_both(w, 20, "mixed", "no exchange")
+    assert_parity(g, o, "mixed")
+    assert np.all(g["elog"] == 255)
+
+
+def test_segment_split_and_explicit_exchange_are_deterministic():
+    pt = _pt()
+    w = I.make_workload([50, 30], [6, 4], [(0.2, 1.5), (0.3, 1.0)], "walk", 91, 0, "mixed",
+                        exchange_every=3)
+    a = pt.Simulation(w, log_capacity=40)
+    a.sweep(33)
+    b = pt.Simulation(w, log_capacity=40)
+    for _ in range(33):
+        b.sweep(1)
+    assert np.array_equal(a.coords(), b.coords())
+    assert np.array_equal(a.logs()[0], b.logs()[0])
+    assert np.array_equal(a.observables()["perm"], b.observables()["perm"])
+    # explicit exchange steps match the oracle's
+    a.exchange()
+    orc = O.Simulation(w)
+    orc.run(33)
+    orc.energy = orc.slot_energies()
+    orc.exchange()
+    assert np.array_equal(a.observables()["perm"], orc.perm)
+    assert a.observables()["e"] == orc.e
