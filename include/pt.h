@@ -182,8 +182,11 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane);
  *   3: FENE term of r2 = x                4: LJ term of r2 = x (FP64 order)
  *   5: FP32 LJ term of r2 from the separation (x, y, 0): out[2i] = value,
  *      out[2i+1] = its error bound (same bound the mixed path uses)
- *   6: Philox block: x = counter words (4 per item, as doubles), y[0] = seed
- *      (as double bit pattern); out[4i..4i+3] = words
+ *   6: Philox block: x = counter words (4 per item, as doubles), y[0], y[1] =
+ *      seed low and high 32 bits (as doubles); out[4i..4i+3] = words
+ *   7: FP64 pairwise tree over each group of 64 consecutive x (the wavefront
+ *      reduction of the kernels), result in every out[i] of the group
+ *   8: the same in FP32 (x rounded to float first); n a multiple of 64 for 7, 8
  * Inputs and outputs are host arrays of n items; synchronous; allocates a
  * temporary device buffer. */
 PT_API int pt_selftest(const pt_model *model, int op, const double *h_x, const double *h_y,

@@ -46,24 +46,19 @@ __device__ __forceinline__ double unit_open(uint32_t w) {
 // Natural logarithm from IEEE operations only.  x = 2^e m with m reduced to
 // [sqrt(1/2), sqrt(2)); f = m - 1 (exact); s = f/(2+f);
 // log m = 2 atanh(s) = 2s + s z Q(z), z = s^2, Q(z) = sum_{k=1..10} 2/(2k+1) z^(k-1)
-// (Horner with fma); log x = e ln2_hi + fma(e, ln2_lo, log m).
+// (Horner with fma); log x = e ln2_hi + fma(e, ln2_lo, log m).  Straight-line
+// code: subnormals are scaled by 2^54 first, and zero, infinity, negative and
+// NaN arguments are patched at the end (-inf, +inf, NaN, NaN).
 __device__ __forceinline__ double det_log(double x) {
-    if (!(x >= 0.0)) return __builtin_nan("");
-    if (x == 0.0) return -__builtin_inf();
-    if (x == __builtin_inf()) return x;
-    uint64_t bits = (uint64_t)__double_as_longlong(x);
-    int ex = 0;
-    if ((bits >> 52) == 0) {
-        x = x * 0x1p54;
-        bits = (uint64_t)__double_as_longlong(x);
-        ex = -54;
-    }
-    ex += (int)(bits >> 52) - 1023;
+    const uint64_t b0 = (uint64_t)__double_as_longlong(x);
+    const bool sub = (b0 >> 52) == 0;
+    const double xs = sub ? x * 0x1p54 : x;
+    const uint64_t bits = (uint64_t)__double_as_longlong(xs);
+    int ex = (int)((bits >> 52) & 0x7FF) - 1023 - (sub ? 54 : 0);
     double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
-    if (m >= 0x1.6a09e667f3bcdp+0) {
-        m = m * 0.5;
-        ex += 1;
-    }
+    const bool hi = m >= 0x1.6a09e667f3bcdp+0;
+    m = hi ? m * 0.5 : m;
+    ex += hi ? 1 : 0;
     const double f = m - 1.0;
     const double s = f / (2.0 + f);
     const double z = s * s;
@@ -79,7 +74,11 @@ __device__ __forceinline__ double det_log(double x) {
     q = __builtin_fma(q, z, 2.0 / 3.0);
     const double lm = __builtin_fma(s * z, q, 2.0 * s);
     const double de = (double)ex;
-    return de * 0x1.62e42fee00000p-1 + __builtin_fma(de, 0x1.a39ef35793c76p-33, lm);
+    double r = de * 0x1.62e42fee00000p-1 + __builtin_fma(de, 0x1.a39ef35793c76p-33, lm);
+    r = (x == 0.0) ? -__builtin_inf() : r;
+    r = (x == __builtin_inf()) ? x : r;
+    r = (x >= 0.0) ? r : __builtin_nan("");
+    return r;
 }
 
 // ------------------------------------------------------- pair / bond terms --
@@ -100,8 +99,8 @@ __device__ __forceinline__ double fene64(const Consts &k, double r2) {
     const double r = __builtin_sqrt(r2);
     const double x = (r - k.r0) / k.R;
     const double y = __builtin_fma(-x, x, 1.0);
-    if (!(y > 0.0)) return __builtin_inf();
-    return k.fene_cf * det_log(y);
+    const double v = k.fene_cf * det_log(y);
+    return (y > 0.0) ? v : __builtin_inf();
 }
 
 // FP32 Lennard-Jones term from an FP64 separation, and b = s6^2 + s6 that
@@ -138,18 +137,64 @@ __device__ __forceinline__ Lj32 lj32(const Consts &k, double dx, double dy, doub
 }
 
 // ------------------------------------------------------ wave reductions --
-// Butterfly over the 64 lanes: after level L every lane holds the sum of its
-// aligned block of 2^L lanes, each node formed as (left + right) in either
-// operand order (IEEE addition commutes), i.e. the pairwise tree over lanes.
+// Pairwise tree over the 64 lanes, all in registers.  Level L adds the value
+// of the partner lane block of size 2^(L-1): quad permutations for levels 1-2,
+// the half-row and row mirrors for levels 3-4 (after level 2 every lane of a
+// quad holds the quad's sum, so a mirror reaches the partner quad; likewise
+// for 8-lane groups), and the gfx950 row-swap instructions for levels 5-6
+// (v_permlane16_swap / v_permlane32_swap applied to two copies of the value
+// leave the lower and the upper block's sums in the two outputs).  Every node
+// is (lower block + upper block) up to operand order, and IEEE addition
+// commutes: the result is the pairwise tree, the same in every lane.
+__device__ __forceinline__ uint32_t dpp_qp1(uint32_t v) { return __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t dpp_qp2(uint32_t v) { return __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t dpp_hmir(uint32_t v) { return __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t dpp_mir(uint32_t v) { return __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false); }
+
+template <uint32_t (*OP)(uint32_t)>
+__device__ __forceinline__ double dpp64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = OP((uint32_t)b), hi = OP((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double join64(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_tree(double v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
+    v = v + dpp64<dpp_qp1>(v);
+    v = v + dpp64<dpp_qp2>(v);
+    v = v + dpp64<dpp_hmir>(v);
+    v = v + dpp64<dpp_mir>(v);
+    {
+        const uint64_t b = (uint64_t)__double_as_longlong(v);
+        const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)b, (uint32_t)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+        v = join64(lo[0], hi[0]) + join64(lo[1], hi[1]);
+    }
+    {
+        const uint64_t b = (uint64_t)__double_as_longlong(v);
+        const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+        v = join64(lo[0], hi[0]) + join64(lo[1], hi[1]);
+    }
     return v;
 }
 
 __device__ __forceinline__ float wave_tree(float v) {
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
+    v = v + __uint_as_float(dpp_qp1(__float_as_uint(v)));
+    v = v + __uint_as_float(dpp_qp2(__float_as_uint(v)));
+    v = v + __uint_as_float(dpp_hmir(__float_as_uint(v)));
+    v = v + __uint_as_float(dpp_mir(__float_as_uint(v)));
+    {
+        const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
+    {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
     return v;
 }
 

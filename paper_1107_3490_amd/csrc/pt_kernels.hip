@@ -69,55 +69,84 @@ __device__ __forceinline__ double bound_energy(const Consts &k, int log_np, int 
     return 0x1p-51 * (double)(2 * log_np + 4) * (dabs(e) + b + 2.0 * pairs * k.neg_floor);
 }
 
-// FP64-order energy E(C) of Eq. (4) for the replica in LDS.
+// Pushes value v as leaf number `idx` (0, 1, 2, ... in order) of a pairwise
+// tree kept as a binary counter: stk[l] holds the pending left sibling of
+// size 2^l.  idx is uniform across the wavefront; after leaf 2^L - 1 the
+// complete tree over 2^L leaves sits in stk[L].
+template <int LEVELS>
+__device__ __forceinline__ void tree_push(double (&stk)[LEVELS + 1], int idx, double v) {
+    double carry = v;
+    bool placed = false;
+#pragma unroll
+    for (int l = 0; l <= LEVELS; ++l) {
+        if (!placed) {
+            if ((idx >> l) & 1) {
+                carry = stk[l] + carry;
+            } else {
+                stk[l] = carry;
+                placed = true;
+            }
+        }
+    }
+}
+
+// Pairwise tree over 64 consecutive leaves j = j0 + jj of row i (zero unless
+// i < j < n), the leaves computed in registers from LDS broadcasts.
+template <int B, int LO, int HI>
+__device__ __forceinline__ double row_chunk(const double *X, const double *Y, const double *Z,
+                                            const Consts &k, int i, int n, int j0, double xi,
+                                            double yi, double zi) {
+    if constexpr (HI - LO == 1) {
+        const int j = j0 + LO;
+        const int a = Geo<B>::pos(j);
+        const double v = lj64(k, sq3(X[a] - xi, Y[a] - yi, Z[a] - zi));
+        return (j > i && j < n) ? v : 0.0;
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        const double l = row_chunk<B, LO, MID>(X, Y, Z, k, i, n, j0, xi, yi, zi);
+        const double r = row_chunk<B, MID, HI>(X, Y, Z, k, i, n, j0, xi, yi, zi);
+        return l + r;
+    }
+}
+
+// FP64-order energy E(C) of Eq. (4) for the replica in LDS.  Lane l computes
+// the rows i of its own contiguous block [l B, (l+1) B): each row is the tree
+// over j in chunks of 64 (static trees, chained by a binary counter), the
+// lane's rows feed a binary counter over its block, and the butterfly over
+// lanes completes the tree over all NP rows.
 template <int B>
 __device__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
                               const Consts &k) {
     using G = Geo<B>;
+    constexpr int CH = G::NP / 64;  // chunks of 64 leaves per row (= B)
+    constexpr int LC = G::LOG;      // levels of the chunk counter
     const int lane = threadIdx.x;
-    // Rows i of the LJ part, pushed into a binary-counter pairwise tree over
-    // NP rows (rows past the chain end are zero).
-    double stk[G::LOG_NP + 1];
+    double blk[LC + 1];
 #pragma unroll
-    for (int l = 0; l <= G::LOG_NP; ++l) stk[l] = 0.0;
-    for (int i = 0; i < G::NP; ++i) {
-        double r = 0.0;
-        if (i < n) {
-            const int ai = G::pos(i);
-            const double xi = X[ai], yi = Y[ai], zi = Z[ai];
-            r = lane_tree<0, B>([&](int b) {
-                const int j = lane * B + b;
-                const int a = b * 64 + lane;
-                const double v = lj64(k, sq3(X[a] - xi, Y[a] - yi, Z[a] - zi));
-                return (j > i && j < n) ? v : 0.0;
-            });
-            r = wave_tree(r);
-        }
-        double carry = r;
-        bool placed = false;
+    for (int l = 0; l <= LC; ++l) blk[l] = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const int i = lane * B + b;
+        const int a = b * 64 + lane;
+        const double xi = X[a], yi = Y[a], zi = Z[a];
+        double row[LC + 1];
 #pragma unroll
-        for (int l = 0; l <= G::LOG_NP; ++l) {
-            if (!placed) {
-                if ((i >> l) & 1) {
-                    carry = stk[l] + carry;
-                } else {
-                    stk[l] = carry;
-                    placed = true;
-                }
-            }
+        for (int l = 0; l <= LC; ++l) row[l] = 0.0;
+        for (int c = 0; c < CH; ++c) {
+            const double v = row_chunk<B, 0, 64>(X, Y, Z, k, i, n, c * 64, xi, yi, zi);
+            tree_push<LC>(row, c, v);
         }
+        tree_push<LC>(blk, b, (CH == 1) ? row[0] : row[LC]);
     }
-    const double e_lj = stk[G::LOG_NP];
+    const double e_lj = wave_tree((B == 1) ? blk[0] : blk[LC]);
     // FENE part: bonds (i, i+1), i < n - 1, lane blocks, then the butterfly.
-    double fb = lane_tree<0, B>([&](int b) {
+    const double fb = lane_tree<0, B>([&](int b) {
         const int i = lane * B + b;
         const int i0 = (i < n - 1) ? i : 0;
         const int a0 = G::pos(i0), a1 = G::pos(i0 + 1);
         const double v = fene64(k, sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]));
         return (i < n - 1) ? v : 0.0;
     });
-    fb = wave_tree(fb);
-    return e_lj + fb;
+    return e_lj + wave_tree(fb);
 }
 
 template <int B>
@@ -183,77 +212,82 @@ __global__ __launch_bounds__(64) void k_sweep(const Tables T, const int32_t *__r
             const double xo = X[ak], yo = Y[ak], zo = Z[ak];
             const double xn = xo + dx, yn = yo + dy, zn = zo + dz;
 
-            // Bond terms on lanes 0..3: (k-1,k) new/old, (k,k+1) new/old.
-            double fv = 0.0;
-            if (lane < 4) {
-                const int nbr = (lane < 2) ? k - 1 : k + 1;
-                if (nbr >= 0 && nbr < n) {
-                    const int an = G::pos(nbr);
-                    const bool nw = (lane & 1) == 0;
-                    fv = fene64(K, sq3(X[an] - (nw ? xn : xo), Y[an] - (nw ? yn : yo),
-                                       Z[an] - (nw ? zn : zo)));
-                }
-            }
-            const double dfl = read_lane(fv, 0) - read_lane(fv, 1);
-            const double dfr = read_lane(fv, 2) - read_lane(fv, 3);
-            const double df = dfl + dfr;
+            // Bond terms: lane & 3 picks (k-1,k) new/old, (k,k+1) new/old; the
+            // other lanes repeat lanes 0..3.  Straight-line code, so that it
+            // overlaps the pair loop.
+            const int nbr = (lane & 2) ? k + 1 : k - 1;
+            const bool has = nbr >= 0 && nbr < n;
+            const int an = G::pos(has ? nbr : k);
+            const bool nw = (lane & 1) == 0;
+            const double fb = fene64(K, sq3(X[an] - (nw ? xn : xo), Y[an] - (nw ? yn : yo),
+                                            Z[an] - (nw ? zn : zo)));
+            const double fv = has ? fb : 0.0;
 
+            // The moved bead's own slot holds the sentinel during its pair loop.
+            wave_sync();
+            if (lane == 0) X[ak] = SENTINEL;
+            wave_sync();
+            auto leaf64 = [&](int b) {
+                const int a = b * 64 + lane;
+                const double xj = X[a], yj = Y[a], zj = Z[a];
+                const double en = lj64(K, sq3(xj - xn, yj - yn, zj - zn));
+                const double eo = lj64(K, sq3(xj - xo, yj - yo, zj - zo));
+                const double tt = en - eo;
+                return Leaf64{tt, dabs(tt)};
+            };
             bool acc = false;
             double de_used = 0.0, bm = 0.0;
-            if (df != __builtin_inf()) {  // a broken bond is always rejected
-                wave_sync();
-                if (lane == 0) X[ak] = SENTINEL;
-                wave_sync();
-                auto leaf64 = [&](int b) {
+            bool exact = !MIXED;
+            if constexpr (MIXED) {
+                const LeafMx s = lane_tree<0, B>([&](int b) {
                     const int a = b * 64 + lane;
                     const double xj = X[a], yj = Y[a], zj = Z[a];
-                    const double en = lj64(K, sq3(xj - xn, yj - yn, zj - zn));
-                    const double eo = lj64(K, sq3(xj - xo, yj - yo, zj - zo));
-                    const double tt = en - eo;
-                    return Leaf64{tt, dabs(tt)};
-                };
-                bool exact = !MIXED;
-                if constexpr (MIXED) {
-                    const LeafMx s = lane_tree<0, B>([&](int b) {
-                        const int a = b * 64 + lane;
-                        const double xj = X[a], yj = Y[a], zj = Z[a];
-                        const Lj32 pn = lj32(K, xj - xn, yj - yn, zj - zn);
-                        const Lj32 po = lj32(K, xj - xo, yj - yo, zj - zo);
-                        return LeafMx{(double)(pn.e - po.e), pn.b + po.b};
-                    });
-                    const double sm = wave_tree(s.t);
-                    const double bs = K.kbound * (double)wave_tree(s.b);
-                    const double dem = sm + df;
-                    const double bt = bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem);
-                    const double lo = dem - bt, hi = dem + bt;
-                    const bool sure_acc = (hi <= 0.0) || (beta * hi < th);
-                    const bool sure_rej = (lo > 0.0) && !(beta * lo < th);
-                    if (finite(bt) && finite(dem) && (sure_acc || sure_rej)) {
-                        acc = sure_acc;
-                        de_used = dem;
-                        bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
-                    } else {
-                        exact = true;
-                        ++n_rescore;
-                    }
+                    const Lj32 pn = lj32(K, xj - xn, yj - yn, zj - zn);
+                    const Lj32 po = lj32(K, xj - xo, yj - yo, zj - zo);
+                    return LeafMx{(double)(pn.e - po.e), pn.b + po.b};
+                });
+                const double sm = wave_tree(s.t);
+                const double bs = K.kbound * (double)wave_tree(s.b);
+                const double dfl = read_lane(fv, 0) - read_lane(fv, 1);
+                const double dfr = read_lane(fv, 2) - read_lane(fv, 3);
+                const double df = dfl + dfr;
+                const double dem = sm + df;
+                const double bt = bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem);
+                const double lo = dem - bt, hi = dem + bt;
+                const bool sure_acc = (hi <= 0.0) || (beta * hi < th);
+                const bool sure_rej = (lo > 0.0) && !(beta * lo < th);
+                if (df == __builtin_inf()) {
+                    acc = false;  // a broken bond is rejected whatever the pair sum
+                } else if (finite(bt) && finite(dem) && (sure_acc || sure_rej)) {
+                    acc = sure_acc;
+                    de_used = dem;
+                    bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
+                } else {
+                    exact = true;
+                    ++n_rescore;
                 }
-                if (exact) {
-                    const Leaf64 s = lane_tree<0, B>(leaf64);
-                    const double sc = wave_tree(s.t);
-                    const double ab = wave_tree(s.a);
-                    const double de = sc + df;
-                    acc = (de <= 0.0) || (beta * de < th);
-                    de_used = de;
-                    bm = bound64(G::LOG_NP, ab, dfl, dfr, de);
-                }
-                wave_sync();
-                if (lane == 0) X[ak] = acc ? xn : xo;
-                if (acc && lane == 0) {
+            }
+            if (exact) {
+                const Leaf64 s = lane_tree<0, B>(leaf64);
+                const double sc = wave_tree(s.t);
+                const double ab = wave_tree(s.a);
+                const double dfl = read_lane(fv, 0) - read_lane(fv, 1);
+                const double dfr = read_lane(fv, 2) - read_lane(fv, 3);
+                const double df = dfl + dfr;
+                const double de = sc + df;
+                acc = (de <= 0.0) || (beta * de < th);
+                de_used = de;
+                bm = bound64(G::LOG_NP, ab, dfl, dfr, de);
+            }
+            wave_sync();
+            if (lane == 0) {
+                X[ak] = acc ? xn : xo;
+                if (acc) {
                     Y[ak] = yn;
                     Z[ak] = zn;
                 }
-                wave_sync();
             }
+            wave_sync();
             if (acc) {
                 E = E + de_used;
                 Bd = Bd + bm + 0x1p-52 * dabs(E);
@@ -426,6 +460,12 @@ __global__ void k_advance(const Tables T, int exchange_only) {
 __global__ void k_selftest(const Consts k, int op, const double *x, const double *y, double *out,
                            int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (op == 7 || op == 8) {
+        // Whole wavefronts: n is a multiple of 64 (checked by the host).
+        if (i - (int64_t)(threadIdx.x & 63) >= n) return;
+        out[i] = (op == 7) ? wave_tree(x[i]) : (double)wave_tree((float)x[i]);
+        return;
+    }
     if (i >= n) return;
     switch (op) {
         case 0: out[i] = __builtin_sqrt(x[i]); break;

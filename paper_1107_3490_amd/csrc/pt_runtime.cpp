@@ -592,7 +592,8 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl) {
 
 PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const double *hy, double *hout, int64_t n) {
     if (model == nullptr || hx == nullptr || hout == nullptr || n < 0) return fail(PT_EINVAL, "bad argument");
-    if (op < 0 || op > 6) return fail(PT_EINVAL, "unknown op %d", op);
+    if (op < 0 || op > 8) return fail(PT_EINVAL, "unknown op %d", op);
+    if ((op == 7 || op == 8) && n % 64 != 0) return fail(PT_EINVAL, "op %d needs n a multiple of 64", op);
     if (n == 0) return PT_OK;
     const pt::Consts k = make_consts(model, true);
     const size_t nin = (op == 6) ? 4 * (size_t)n : (size_t)n;

@@ -25,7 +25,7 @@ PT_OK, PT_EINVAL, PT_EDOMAIN, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EUNSUPPORTED = 0
 PT_FP64, PT_MIXED = 0, 1
 
 # Diagnostic ops of pt_selftest.
-OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX = range(7)
+OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32 = range(9)
 
 EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_sweep", "pt_exchange", "pt_energy",
            "pt_observables", "pt_reset_observables", "pt_get_coords", "pt_get_running",

@@ -108,6 +108,29 @@ def test_device_arithmetic_matches_host():
     assert np.array_equal(out, want)
 
 
+def _pairwise(v):
+    while len(v) > 1:
+        v = [v[i] + v[i + 1] for i in range(0, len(v), 2)]
+    return v[0]
+
+
+def test_wavefront_reduction_is_the_pairwise_tree():
+    """The kernels' 64-lane reduction equals the pairwise tree over lanes, bit
+    for bit, in FP64 and FP32 (values spanning many magnitudes and signs, so a
+    different association order would show)."""
+    pt = _pt()
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(64 * 200) * np.exp(rng.uniform(-30, 30, 64 * 200))
+    got = pt.pt_selftest(I.model_params(), pt.OP_WAVE64, x).reshape(-1, 64)
+    for grp, row in zip(x.reshape(-1, 64), got):
+        want = _pairwise(list(grp))
+        assert np.all(row == want)
+    got32 = pt.pt_selftest(I.model_params(), pt.OP_WAVE32, x).reshape(-1, 64)
+    for grp, row in zip(x.reshape(-1, 64), got32):
+        want = _pairwise([np.float32(v) for v in grp])
+        assert np.all(row == np.float64(want))
+
+
 def test_fp32_term_bound_is_sound():
     """The per-term error bound the mixed path relies on, on random pair geometries
     (near contact, around the minimum, around the cutoff, far)."""
