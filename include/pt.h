@@ -173,9 +173,10 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
 PT_API int pt_time_sweeps(pt_handle *h, int64_t n_sweeps, double *sweep_ms, double *total_ms,
                           int64_t *launches);
 
-/* Mapping chosen for each chain: beads per lane (a power of two) so that a
- * 64-lane wavefront covers the chain.  [n_chains]. */
-PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane);
+/* Mapping chosen for each chain (either pointer may be NULL): beads per lane
+ * (a power of two <= 8) and wavefronts per replica (1, 2 or 4), the smallest
+ * pair with 64 * wpr * bpl >= N.  [n_chains] each. */
+PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_per_replica);
 
 /* Diagnostics of the device arithmetic (used by the test suite).  op:
  *   0: IEEE sqrt      1: IEEE x/y        2: deterministic log

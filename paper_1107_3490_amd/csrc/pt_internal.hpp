@@ -40,7 +40,7 @@ struct Tables {
     int64_t *counts;             // [g][PT_NCOUNTS] see pt_observables
     const int64_t *word_off;     // accept-log word offset of slot g
     // per conformation q (conformation q starts in slot q)
-    double *coords;              // swizzled SoA, bead j at (j mod B) * 64 + j / B
+    double *coords;              // swizzled SoA, bead j at (j mod B) * 64 W + j / B
     const int64_t *coord_off;    // start of conformation q in coords
     double *e_run;               // running energy
     double *b_run;               // bound on |e_run - exact sum of the FP64 terms|
@@ -64,13 +64,14 @@ struct Tables {
     Consts k;
 };
 
-// Kernel launchers (pt_kernels.hip).  bpl = beads per lane of the class,
-// list = global slots (sweep), conformations (energy) or chains (exchange).
-hipError_t launch_sweep(int bpl, bool mixed, const Tables &T, const int32_t *slot_list,
+// Kernel launchers (pt_kernels.hip).  A class is (bpl, wpr): beads per lane
+// and wavefronts per replica; list = global slots (sweep), conformations or
+// slots (energy) or chains (exchange) of that class.
+hipError_t launch_sweep(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *slot_list,
                         int n_items, hipStream_t s);
-hipError_t launch_energy(int bpl, const Tables &T, const int32_t *conf_list, int n_items,
+hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *conf_list, int n_items,
                          double *out_e, double *out_b, hipStream_t s);
-hipError_t launch_exchange(int bpl, const Tables &T, const int32_t *chain_list, int n_chains,
+hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *chain_list, int n_chains,
                            int max_pairs, int force, hipStream_t s);
 hipError_t launch_advance(const Tables &T, int force, hipStream_t s);
 hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y,

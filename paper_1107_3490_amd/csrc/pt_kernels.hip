@@ -3,19 +3,19 @@
 // exchange for a bead-spring homopolymer (Gross, Janke, Bachmann,
 // arXiv:1107.3490, Secs. 3.1-3.4).
 //
-// Mapping.  One 64-lane wavefront owns one replica for a whole sweep.  The
-// replica's FP64 coordinates live in LDS in a swizzled SoA layout: bead j of a
-// chain whose class has B beads per lane sits at (j mod B) * 64 + j / B, so
-// lane l owns the contiguous bead block [l B, (l+1) B) and, for a fixed b, the
-// 64 lanes touch 64 consecutive doubles (no bank conflicts).  The same layout
-// is kept in HBM, so loading and storing a replica are straight coalesced
-// copies.  Beads past the chain end hold a far-away sentinel x coordinate, and
-// the moved bead's slot holds it during its own pair loop, so every pair term
-// of a padded or excluded bead is an exact zero without a per-pair mask.
+// Mapping.  A replica is owned by W wavefronts (W = 1, 2 or 4; 64 W lanes),
+// each lane holding the contiguous bead block [t B, (t+1) B) of the padded
+// range of NP = 64 W B beads (t = thread index in the block, B <= 8), in
+// registers.  LDS mirrors the replica's FP64 coordinates in a swizzled SoA
+// layout -- bead j at (j mod B) 64 W + j / B -- so that block-wide copies and
+// the per-bead accesses of the 64 W lanes touch consecutive doubles; HBM keeps
+// the same layout.  Beads past the chain end hold a far-away sentinel x
+// coordinate, so their pair terms are exact zeros.
 //
-// The pair sum of a move is the pairwise tree over the lane's contiguous block
-// followed by the butterfly over lanes: the FP64-order sum of the public header
-// for every beads-per-lane choice.
+// The pair sum of a move is the pairwise tree over each lane's block, the
+// register butterfly over the 64 lanes of a wavefront, and the pairwise tree
+// over the W wavefront sums: the FP64-order sum of the public header for
+// every (B, W).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,14 +26,18 @@ namespace pt {
 
 namespace {
 
-constexpr double SENTINEL = 1.0e30;
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
-template <int B>
+template <int B, int W>
 struct Geo {
-    static constexpr int NP = 64 * B;
-    static constexpr int LOG = (B == 1) ? 0 : (B == 2) ? 1 : (B == 4) ? 2 : (B == 8) ? 3 : (B == 16) ? 4 : 5;
-    static constexpr int LOG_NP = 6 + LOG;
-    __device__ static __forceinline__ int pos(int j) { return ((j & (B - 1)) << 6) | (j >> LOG); }
+    static constexpr int NT = 64 * W;  // lanes owning the replica in a sweep
+    static constexpr int NP = NT * B;  // padded bead range
+    static constexpr int LOGB = ilog2(B);
+    static constexpr int LOGW = ilog2(W);
+    static constexpr int LOG_NP = 6 + LOGW + LOGB;
+    __device__ static __forceinline__ int pos(int j) {
+        return ((j & (B - 1)) << (6 + LOGW)) | (j >> LOGB);
+    }
 };
 
 struct Leaf64 {
@@ -69,10 +73,10 @@ __device__ __forceinline__ double bound_energy(const Consts &k, int log_np, int 
     return 0x1p-51 * (double)(2 * log_np + 4) * (dabs(e) + b + 2.0 * pairs * k.neg_floor);
 }
 
-// Pushes value v as leaf number `idx` (0, 1, 2, ... in order) of a pairwise
-// tree kept as a binary counter: stk[l] holds the pending left sibling of
-// size 2^l.  idx is uniform across the wavefront; after leaf 2^L - 1 the
-// complete tree over 2^L leaves sits in stk[L].
+// Pushes v as leaf number idx (0, 1, 2, ... in order) of a pairwise tree kept
+// as a binary counter: stk[l] holds the pending left sibling of size 2^l.
+// idx is uniform across the wavefront; after leaf 2^L - 1 the complete tree
+// over 2^L leaves sits in stk[L].
 template <int LEVELS>
 __device__ __forceinline__ void tree_push(double (&stk)[LEVELS + 1], int idx, double v) {
     double carry = v;
@@ -90,57 +94,63 @@ __device__ __forceinline__ void tree_push(double (&stk)[LEVELS + 1], int idx, do
     }
 }
 
-// Pairwise tree over 64 consecutive leaves j = j0 + jj of row i (zero unless
-// i < j < n), the leaves computed in registers from LDS broadcasts.
-template <int B, int LO, int HI>
+// Pairwise tree over the 64 leaves j = j0 .. j0+63 of row i (zero unless
+// i < j < n), computed in registers from LDS broadcasts.
+template <int B, int W, int LO, int HI>
 __device__ __forceinline__ double row_chunk(const double *X, const double *Y, const double *Z,
                                             const Consts &k, int i, int n, int j0, double xi,
                                             double yi, double zi) {
     if constexpr (HI - LO == 1) {
         const int j = j0 + LO;
-        const int a = Geo<B>::pos(j);
+        const int a = Geo<B, W>::pos(j);
         const double v = lj64(k, sq3(X[a] - xi, Y[a] - yi, Z[a] - zi));
         return (j > i && j < n) ? v : 0.0;
     } else {
         constexpr int MID = (LO + HI) / 2;
-        const double l = row_chunk<B, LO, MID>(X, Y, Z, k, i, n, j0, xi, yi, zi);
-        const double r = row_chunk<B, MID, HI>(X, Y, Z, k, i, n, j0, xi, yi, zi);
+        const double l = row_chunk<B, W, LO, MID>(X, Y, Z, k, i, n, j0, xi, yi, zi);
+        const double r = row_chunk<B, W, MID, HI>(X, Y, Z, k, i, n, j0, xi, yi, zi);
         return l + r;
     }
 }
 
-// FP64-order energy E(C) of Eq. (4) for the replica in LDS.  Lane l computes
-// the rows i of its own contiguous block [l B, (l+1) B): each row is the tree
-// over j in chunks of 64 (static trees, chained by a binary counter), the
-// lane's rows feed a binary counter over its block, and the butterfly over
-// lanes completes the tree over all NP rows.
-template <int B>
+// FP64-order energy E(C) of Eq. (4) for the replica in LDS, on one wavefront
+// (lanes 0..63 of the calling block).  The rows are taken in aligned blocks of
+// 64: lane l computes row 64 r + l, each row being the tree over j in chunks
+// of 64 (static trees chained by a binary counter; chunks left of the block
+// or past the chain end are exact zeros and are skipped); the butterfly over
+// lanes gives the tree over the block's 64 rows, and a binary counter over r
+// the tree over all NP rows.  Bonds: contiguous lane blocks and the butterfly.
+template <int B, int W>
 __device__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
                               const Consts &k) {
-    using G = Geo<B>;
-    constexpr int CH = G::NP / 64;  // chunks of 64 leaves per row (= B)
-    constexpr int LC = G::LOG;      // levels of the chunk counter
-    const int lane = threadIdx.x;
+    using G = Geo<B, W>;
+    constexpr int BP = B * W;  // 64-row blocks = 64-leaf chunks per row
+    constexpr int LC = ilog2(BP);
+    const int lane = threadIdx.x & 63;
     double blk[LC + 1];
 #pragma unroll
     for (int l = 0; l <= LC; ++l) blk[l] = 0.0;
-    for (int b = 0; b < B; ++b) {
-        const int i = lane * B + b;
-        const int a = b * 64 + lane;
-        const double xi = X[a], yi = Y[a], zi = Z[a];
-        double row[LC + 1];
+    for (int r = 0; r < BP; ++r) {
+        double bv = 0.0;
+        if (r * 64 < n) {
+            const int i = r * 64 + lane;
+            const int ai = G::pos(i);
+            const double xi = X[ai], yi = Y[ai], zi = Z[ai];
+            double row[LC + 1];
 #pragma unroll
-        for (int l = 0; l <= LC; ++l) row[l] = 0.0;
-        for (int c = 0; c < CH; ++c) {
-            const double v = row_chunk<B, 0, 64>(X, Y, Z, k, i, n, c * 64, xi, yi, zi);
-            tree_push<LC>(row, c, v);
+            for (int l = 0; l <= LC; ++l) row[l] = 0.0;
+            for (int c = 0; c < BP; ++c) {
+                double v = 0.0;
+                if (c >= r && c * 64 < n) v = row_chunk<B, W, 0, 64>(X, Y, Z, k, i, n, c * 64, xi, yi, zi);
+                tree_push<LC>(row, c, v);
+            }
+            bv = wave_tree(row[LC]);
         }
-        tree_push<LC>(blk, b, (CH == 1) ? row[0] : row[LC]);
+        tree_push<LC>(blk, r, bv);
     }
-    const double e_lj = wave_tree((B == 1) ? blk[0] : blk[LC]);
-    // FENE part: bonds (i, i+1), i < n - 1, lane blocks, then the butterfly.
-    const double fb = lane_tree<0, B>([&](int b) {
-        const int i = lane * B + b;
+    const double e_lj = blk[LC];
+    const double fb = lane_tree<0, BP>([&](int b) {
+        const int i = lane * BP + b;
         const int i0 = (i < n - 1) ? i : 0;
         const int a0 = G::pos(i0), a1 = G::pos(i0 + 1);
         const double v = fene64(k, sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]));
@@ -149,27 +159,84 @@ __device__ double energy_wave(const double *X, const double *Y, const double *Z,
     return e_lj + wave_tree(fb);
 }
 
-template <int B>
-__device__ __forceinline__ void load_replica(double *X, double *Y, double *Z, const double *src) {
-    using G = Geo<B>;
-    const int lane = threadIdx.x;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        X[b * 64 + lane] = src[b * 64 + lane];
-        Y[b * 64 + lane] = src[G::NP + b * 64 + lane];
-        Z[b * 64 + lane] = src[2 * G::NP + b * 64 + lane];
-    }
-    wave_sync();
+// Squared end-to-end distance and squared radius of gyration (Eq. 8) of the
+// replica in LDS, one wavefront: means and the sum of squares as lane-block
+// trees plus the butterfly.
+template <int B, int W>
+__device__ void shape_wave(const double *X, const double *Y, const double *Z, int n,
+                           double &ree2, double &rg2) {
+    using G = Geo<B, W>;
+    constexpr int BP = B * W;
+    const int lane = threadIdx.x & 63;
+    const int a0 = G::pos(0), a1 = G::pos(n - 1);
+    ree2 = sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]);
+    auto mean = [&](const double *C) {
+        const double s = lane_tree<0, BP>([&](int b) {
+            const int j = lane * BP + b;
+            return (j < n) ? C[G::pos(j)] : 0.0;
+        });
+        return wave_tree(s) / (double)n;
+    };
+    const double mx = mean(X), my = mean(Y), mz = mean(Z);
+    const double s = lane_tree<0, BP>([&](int b) {
+        const int j = lane * BP + b;
+        const int a = G::pos(j);
+        const double v = sq3(X[a] - mx, Y[a] - my, Z[a] - mz);
+        return (j < n) ? v : 0.0;
+    });
+    rg2 = wave_tree(s) / (double)n;
+}
+
+// Copy a replica (x, y, z arrays back to back) with NTH threads of the block.
+template <int B, int W, int NTH>
+__device__ __forceinline__ void copy_replica(double *dst, const double *src) {
+    constexpr int TOT = 3 * Geo<B, W>::NP;
+    for (int i = threadIdx.x; i < TOT; i += NTH) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------ sweep --
+// What the batch prologue knows about one move: its draws, and, at the start
+// of the batch, r_k and the two bond differences.  These stay valid unless an
+// earlier move of the same batch that touched k-1, k or k+1 was accepted;
+// `conflict` lists the earlier moves of the batch with |k' - k| <= 1.
+struct MoveRec {
+    double dx, dy, dz, th;
+    double xo, yo, zo;
+    double dfl, dfr;
+    uint64_t conflict;
+    int k;
+    int pad;
+};
+
+// Sum of the W per-wavefront values v[0..W) as a pairwise tree.
+template <int W>
+__device__ __forceinline__ double tree_w(const double *v) {
+    if constexpr (W == 1) return v[0];
+    else if constexpr (W == 2) return v[0] + v[1];
+    else return (v[0] + v[1]) + (v[2] + v[3]);
+}
+
 // One sweep (N attempted moves, Sec. 3.2) of every slot in `list`, then the
 // per-sweep record of E, Ree^2 and Rg^2 (Eq. 8).
-template <int B, bool MIXED>
-__global__ __launch_bounds__(64) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
-    using G = Geo<B>;
-    __shared__ double X[G::NP], Y[G::NP], Z[G::NP];
-    const int lane = threadIdx.x;
+//
+// Moves are processed in batches.  A vector prologue (wavefront 0, one move
+// per lane) computes the Philox draws, -log u, the gather of r_k and of its
+// bond neighbours, the four bond terms and the conflict mask.  The serial part
+// of a move is then the pair loop over the lane's beads in registers, the
+// butterflies, one barrier to combine the W wavefront sums (W > 1), and the
+// decision, taken identically by every wavefront.
+template <int B, int W, bool MIXED>
+__global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
+    using G = Geo<B, W>;
+    constexpr int NT = G::NT;
+    constexpr int MB = (W >= 4) ? 32 : 64;  // moves per batch (LDS budget at W = 4)
+    __shared__ double XYZ[3 * G::NP];
+    double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
+    __shared__ MoveRec rec[MB];
+    __shared__ double part[2][2][W];
+    __shared__ double partx[2][W];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const Consts &K = T.k;
     const int g = list[blockIdx.x];
     const int c = T.slot_chain[g];
@@ -180,59 +247,113 @@ __global__ __launch_bounds__(64) void k_sweep(const Tables T, const int32_t *__r
     const uint32_t t = (uint32_t)t64;
     const int q = T.perm[g];
     double *cq = T.coords + T.coord_off[q];
-    load_replica<B>(X, Y, Z, cq);
+    copy_replica<B, W, NT>(XYZ, cq);
+    __syncthreads();
+    double rx[B], ry[B], rz[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        rx[b] = X[b * NT + tid];
+        ry[b] = Y[b * NT + tid];
+        rz[b] = Z[b * NT + tid];
+    }
 
     double E = T.e_run[q], Bd = T.b_run[q];
     int64_t n_acc = 0, n_rescore = 0;
     uint64_t *logrow = (T.accept_log != nullptr && t64 < T.log_cap)
                            ? T.accept_log + t64 * T.words_total + T.word_off[g]
                            : nullptr;
+    uint64_t logword = 0;
 
-    for (int m0 = 0; m0 < n; m0 += 64) {
-        // Draws of move m0 + lane (Philox counters (m, t, g, 0) and (m, t, g, 1)).
-        int mk;
-        double mdx, mdy, mdz, mth;
-        {
+    for (int m0 = 0; m0 < n; m0 += MB) {
+        __syncthreads();  // commits of the previous batch visible, rec[] free
+        if (wv == 0) {
+            // ---- prologue: move m0 + lane (Philox counters (m, t, g, 0), (m, t, g, 1))
             const uint32_t m = (uint32_t)(m0 + lane);
             const U4 w = philox10(U4{m, t, gid, 0u}, T.seed);
             const U4 v = philox10(U4{m, t, gid, 1u}, T.seed);
-            mk = (int)(((uint64_t)w.x * (uint64_t)(uint32_t)n) >> 32);
-            mdx = (unit_open(w.y) - 0.5) * K.edge;
-            mdy = (unit_open(w.z) - 0.5) * K.edge;
-            mdz = (unit_open(w.w) - 0.5) * K.edge;
-            mth = -det_log(unit_open(v.x));
-        }
-        const int nb = (n - m0 < 64) ? (n - m0) : 64;
-        uint64_t bits = 0;
-        for (int i = 0; i < nb; ++i) {
-            const int k = read_lane(mk, i);
-            const double dx = read_lane(mdx, i), dy = read_lane(mdy, i), dz = read_lane(mdz, i);
-            const double th = read_lane(mth, i);
+            MoveRec r;
+            r.k = (int)(((uint64_t)w.x * (uint64_t)(uint32_t)n) >> 32);
+            r.dx = (unit_open(w.y) - 0.5) * K.edge;
+            r.dy = (unit_open(w.z) - 0.5) * K.edge;
+            r.dz = (unit_open(w.w) - 0.5) * K.edge;
+            r.th = -det_log(unit_open(v.x));
+            const int k = r.k;
             const int ak = G::pos(k);
-            const double xo = X[ak], yo = Y[ak], zo = Z[ak];
-            const double xn = xo + dx, yn = yo + dy, zn = zo + dz;
+            r.xo = X[ak];
+            r.yo = Y[ak];
+            r.zo = Z[ak];
+            const double xn = r.xo + r.dx, yn = r.yo + r.dy, zn = r.zo + r.dz;
+            const bool hl = k > 0, hr = k + 1 < n;
+            const int al = G::pos(hl ? k - 1 : k), ar = G::pos(hr ? k + 1 : k);
+            const double xl = X[al], yl = Y[al], zl = Z[al];
+            const double xr = X[ar], yr = Y[ar], zr = Z[ar];
+            const double fln = fene64(K, sq3(xl - xn, yl - yn, zl - zn));
+            const double flo = fene64(K, sq3(xl - r.xo, yl - r.yo, zl - r.zo));
+            const double frn = fene64(K, sq3(xr - xn, yr - yn, zr - zn));
+            const double fro = fene64(K, sq3(xr - r.xo, yr - r.yo, zr - r.zo));
+            r.dfl = hl ? fln - flo : 0.0;
+            r.dfr = hr ? frn - fro : 0.0;
+            uint64_t cm = 0;
+            for (int j = 0; j < MB; ++j) {
+                const int dd = read_lane(k, j) - k;
+                cm |= (j < lane && dd >= -1 && dd <= 1) ? (1ull << j) : 0ull;
+            }
+            r.conflict = cm;
+            r.pad = 0;
+            if (lane < MB) rec[lane] = r;
+        }
+        __syncthreads();
+        const int nb = (n - m0 < MB) ? (n - m0) : MB;
+        uint64_t bits = 0;
+        // The last committed move: earlier commits are visible in LDS to every
+        // wavefront, this one possibly not yet to the other wavefronts.
+        int last_k = -1;
+        double lx = 0.0, ly = 0.0, lz = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            const MoveRec r = rec[i];
+            const int k = __builtin_amdgcn_readfirstlane(r.k);
+            const uint64_t cf =
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r.conflict)) |
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(r.conflict >> 32)) << 32);
+            const double th = r.th;
+            double xo = r.xo, yo = r.yo, zo = r.zo, dfl = r.dfl, dfr = r.dfr;
+            if ((cf & bits) != 0) {
+                // An accepted move of this batch touched k-1, k or k+1: redo the
+                // gather and the bond terms from the current replica (lanes 0..3
+                // of each wavefront evaluate (k-1,k) new/old, (k,k+1) new/old).
+                auto fetch = [&](int a, double &x, double &y, double &z) {
+                    const int p = G::pos(a);
+                    x = X[p];
+                    y = Y[p];
+                    z = Z[p];
+                    if (W > 1 && a == last_k) {
+                        x = lx;
+                        y = ly;
+                        z = lz;
+                    }
+                };
+                fetch(k, xo, yo, zo);
+                const double xq = xo + r.dx, yq = yo + r.dy, zq = zo + r.dz;
+                const int nbr = (lane & 2) ? k + 1 : k - 1;
+                const bool has = nbr >= 0 && nbr < n;
+                double xa, ya, za;
+                fetch(has ? nbr : k, xa, ya, za);
+                const bool nw = (lane & 1) == 0;
+                const double fb = fene64(K, sq3(xa - (nw ? xq : xo), ya - (nw ? yq : yo),
+                                                za - (nw ? zq : zo)));
+                const double fv = has ? fb : 0.0;
+                dfl = read_lane(fv, 0) - read_lane(fv, 1);
+                dfr = read_lane(fv, 2) - read_lane(fv, 3);
+            }
+            const double xn = xo + r.dx, yn = yo + r.dy, zn = zo + r.dz;
+            const double df = dfl + dfr;
+            const int owner = k >> G::LOGB, slot = k & (B - 1);
+            const bool mine = (tid == owner);
 
-            // Bond terms: lane & 3 picks (k-1,k) new/old, (k,k+1) new/old; the
-            // other lanes repeat lanes 0..3.  Straight-line code, so that it
-            // overlaps the pair loop.
-            const int nbr = (lane & 2) ? k + 1 : k - 1;
-            const bool has = nbr >= 0 && nbr < n;
-            const int an = G::pos(has ? nbr : k);
-            const bool nw = (lane & 1) == 0;
-            const double fb = fene64(K, sq3(X[an] - (nw ? xn : xo), Y[an] - (nw ? yn : yo),
-                                            Z[an] - (nw ? zn : zo)));
-            const double fv = has ? fb : 0.0;
-
-            // The moved bead's own slot holds the sentinel during its pair loop.
-            wave_sync();
-            if (lane == 0) X[ak] = SENTINEL;
-            wave_sync();
             auto leaf64 = [&](int b) {
-                const int a = b * 64 + lane;
-                const double xj = X[a], yj = Y[a], zj = Z[a];
-                const double en = lj64(K, sq3(xj - xn, yj - yn, zj - zn));
-                const double eo = lj64(K, sq3(xj - xo, yj - yo, zj - zo));
-                const double tt = en - eo;
+                const double en = lj64(K, sq3(rx[b] - xn, ry[b] - yn, rz[b] - zn));
+                const double eo = lj64(K, sq3(rx[b] - xo, ry[b] - yo, rz[b] - zo));
+                const double tt = (mine && b == slot) ? 0.0 : en - eo;
                 return Leaf64{tt, dabs(tt)};
             };
             bool acc = false;
@@ -240,17 +361,25 @@ __global__ __launch_bounds__(64) void k_sweep(const Tables T, const int32_t *__r
             bool exact = !MIXED;
             if constexpr (MIXED) {
                 const LeafMx s = lane_tree<0, B>([&](int b) {
-                    const int a = b * 64 + lane;
-                    const double xj = X[a], yj = Y[a], zj = Z[a];
-                    const Lj32 pn = lj32(K, xj - xn, yj - yn, zj - zn);
-                    const Lj32 po = lj32(K, xj - xo, yj - yo, zj - zo);
-                    return LeafMx{(double)(pn.e - po.e), pn.b + po.b};
+                    const Lj32 pn = lj32(K, rx[b] - xn, ry[b] - yn, rz[b] - zn);
+                    const Lj32 po = lj32(K, rx[b] - xo, ry[b] - yo, rz[b] - zo);
+                    const bool self = mine && b == slot;
+                    const float tt = self ? 0.0f : pn.e - po.e;
+                    const float bb = self ? 0.0f : pn.b + po.b;
+                    return LeafMx{(double)tt, bb};
                 });
-                const double sm = wave_tree(s.t);
-                const double bs = K.kbound * (double)wave_tree(s.b);
-                const double dfl = read_lane(fv, 0) - read_lane(fv, 1);
-                const double dfr = read_lane(fv, 2) - read_lane(fv, 3);
-                const double df = dfl + dfr;
+                double sm = wave_tree(s.t);
+                double bsum = (double)wave_tree(s.b);
+                if constexpr (W > 1) {
+                    if (lane == 0) {
+                        part[i & 1][0][wv] = sm;
+                        part[i & 1][1][wv] = bsum;
+                    }
+                    __syncthreads();
+                    sm = tree_w<W>(part[i & 1][0]);
+                    bsum = tree_w<W>(part[i & 1][1]);
+                }
+                const double bs = K.kbound * bsum;
                 const double dem = sm + df;
                 const double bt = bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem);
                 const double lo = dem - bt, hi = dem + bt;
@@ -269,87 +398,92 @@ __global__ __launch_bounds__(64) void k_sweep(const Tables T, const int32_t *__r
             }
             if (exact) {
                 const Leaf64 s = lane_tree<0, B>(leaf64);
-                const double sc = wave_tree(s.t);
-                const double ab = wave_tree(s.a);
-                const double dfl = read_lane(fv, 0) - read_lane(fv, 1);
-                const double dfr = read_lane(fv, 2) - read_lane(fv, 3);
-                const double df = dfl + dfr;
+                double sc = wave_tree(s.t);
+                double ab = wave_tree(s.a);
+                if constexpr (W > 1) {
+                    double *pp = MIXED ? partx[0] : part[i & 1][0];
+                    double *pa = MIXED ? partx[1] : part[i & 1][1];
+                    if (lane == 0) {
+                        pp[wv] = sc;
+                        pa[wv] = ab;
+                    }
+                    __syncthreads();
+                    sc = tree_w<W>(pp);
+                    ab = tree_w<W>(pa);
+                }
                 const double de = sc + df;
                 acc = (de <= 0.0) || (beta * de < th);
                 de_used = de;
                 bm = bound64(G::LOG_NP, ab, dfl, dfr, de);
             }
-            wave_sync();
-            if (lane == 0) {
-                X[ak] = acc ? xn : xo;
-                if (acc) {
+            if (acc) {
+                if (mine) {
+                    const int ak = G::pos(k);
+                    X[ak] = xn;
                     Y[ak] = yn;
                     Z[ak] = zn;
                 }
-            }
-            wave_sync();
-            if (acc) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const bool me = mine && b == slot;
+                    rx[b] = me ? xn : rx[b];
+                    ry[b] = me ? yn : ry[b];
+                    rz[b] = me ? zn : rz[b];
+                }
                 E = E + de_used;
                 Bd = Bd + bm + 0x1p-52 * dabs(E);
                 ++n_acc;
                 bits |= 1ull << i;
+                last_k = k;
+                lx = xn;
+                ly = yn;
+                lz = zn;
+            } else {
+                last_k = -1;
             }
+            wave_sync();
         }
-        if (logrow != nullptr && lane == 0) logrow[m0 >> 6] = bits;
+        logword |= bits << (m0 & 63);
+        if (logrow != nullptr && tid == 0 && (((m0 + MB) & 63) == 0 || m0 + MB >= n))
+            logrow[m0 >> 6] = logword;
+        if (((m0 + MB) & 63) == 0) logword = 0;
     }
 
-    // Write the replica back; record the sweep (before any exchange).
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        cq[b * 64 + lane] = X[b * 64 + lane];
-        cq[G::NP + b * 64 + lane] = Y[b * 64 + lane];
-        cq[2 * G::NP + b * 64 + lane] = Z[b * 64 + lane];
-    }
-    // Re-synchronise the running energy with the FP64-order energy when its
-    // bound has grown past resync_rel of max(1, |E|) (after a start with
-    // near-overlapping beads, or after many accepted moves).
-    bool resync = false;
-    if (!(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
-        E = energy_wave<B>(X, Y, Z, n, K);
-        Bd = bound_energy(K, G::LOG_NP, n, E, 0.0);
-        resync = true;
-    }
-    const int a0 = G::pos(0), a1 = G::pos(n - 1);
-    const double ree2 = sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]);
-    auto mean = [&](const double *C) {
-        double s = lane_tree<0, B>([&](int b) {
-            const int j = lane * B + b;
-            return (j < n) ? C[b * 64 + lane] : 0.0;
-        });
-        return wave_tree(s) / (double)n;
-    };
-    const double mx = mean(X), my = mean(Y), mz = mean(Z);
-    double rg = lane_tree<0, B>([&](int b) {
-        const int j = lane * B + b;
-        const int a = b * 64 + lane;
-        const double v = sq3(X[a] - mx, Y[a] - my, Z[a] - mz);
-        return (j < n) ? v : 0.0;
-    });
-    const double rg2 = wave_tree(rg) / (double)n;
-    if (lane == 0) {
-        T.e_run[q] = E;
-        T.b_run[q] = Bd;
-        int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
-        cnt[0] += n_acc;
-        cnt[3] += n_rescore;
-        cnt[5] += n;
-        cnt[6] += resync ? 1 : 0;
-        double *ac = T.acc + (int64_t)g * 5;
-        ac[0] += 1.0;
-        ac[1] += E;
-        ac[2] += E * E;
-        ac[3] += rg2;
-        ac[4] += ree2;
-        if (T.series != nullptr && t64 < T.series_cap) {
-            double *row = T.series + (t64 * T.total_slots + g) * 3;
-            row[0] = E;
-            row[1] = ree2;
-            row[2] = rg2;
+    // Write the replica back; record the sweep (before any exchange); re-sync
+    // the running energy with the FP64-order energy when its bound has grown past
+    // resync_rel of max(1, |E|) (a start with near-overlapping beads, or many
+    // accepted moves).
+    __syncthreads();
+    copy_replica<B, W, NT>(cq, XYZ);
+    if (wv == 0) {
+        double ree2, rg2;
+        shape_wave<B, W>(X, Y, Z, n, ree2, rg2);
+        bool resync = false;
+        if (!(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
+            E = energy_wave<B, W>(X, Y, Z, n, K);
+            Bd = bound_energy(K, G::LOG_NP, n, E, 0.0);
+            resync = true;
+        }
+        if (lane == 0) {
+            T.e_run[q] = E;
+            T.b_run[q] = Bd;
+            int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
+            cnt[0] += n_acc;
+            cnt[3] += n_rescore;
+            cnt[5] += n;
+            cnt[6] += resync ? 1 : 0;
+            double *ac = T.acc + (int64_t)g * 5;
+            ac[0] += 1.0;
+            ac[1] += E;
+            ac[2] += E * E;
+            ac[3] += rg2;
+            ac[4] += ree2;
+            if (T.series != nullptr && t64 < T.series_cap) {
+                double *row = T.series + (t64 * T.total_slots + g) * 3;
+                row[0] = E;
+                row[1] = ree2;
+                row[2] = rg2;
+            }
         }
     }
 }
@@ -357,17 +491,19 @@ __global__ __launch_bounds__(64) void k_sweep(const Tables T, const int32_t *__r
 // ----------------------------------------------------------------- energy --
 // FP64-order energy of the conformations in `list` (by_slot: list holds slots
 // and the conformation is perm[g]); writes out_e / out_b indexed like list.
-template <int B>
+template <int B, int W>
 __global__ __launch_bounds__(64) void k_energy(const Tables T, const int32_t *__restrict__ list,
                                                double *out_e, double *out_b, int by_slot) {
-    using G = Geo<B>;
-    __shared__ double X[G::NP], Y[G::NP], Z[G::NP];
+    using G = Geo<B, W>;
+    __shared__ double XYZ[3 * G::NP];
+    double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
     const int id = list[blockIdx.x];
     const int q = by_slot ? T.perm[id] : id;
     const int c = T.slot_chain[q];  // conformation q started in slot q: same chain
     const int n = T.chain_n[c];
-    load_replica<B>(X, Y, Z, T.coords + T.coord_off[q]);
-    const double e = energy_wave<B>(X, Y, Z, n, T.k);
+    copy_replica<B, W, 64>(XYZ, T.coords + T.coord_off[q]);
+    wave_sync();
+    const double e = energy_wave<B, W>(X, Y, Z, n, T.k);
     if (threadIdx.x == 0) {
         out_e[id] = e;
         if (out_b != nullptr) out_b[id] = bound_energy(T.k, G::LOG_NP, n, e, 0.0);
@@ -375,15 +511,17 @@ __global__ __launch_bounds__(64) void k_energy(const Tables T, const int32_t *__
 }
 
 // --------------------------------------------------------------- exchange --
-// One exchange step (Sec. 3.3, Eq. 6) for the chains in `list`: wave p of a
-// chain handles the pair (i, i+1), i = (e mod 2) + 2p.  The decision is taken
-// from the running energies when their bounds settle it, otherwise from the
-// FP64-order energies of both conformations (which also re-synchronise them).
-template <int B>
+// One exchange step (Sec. 3.3, Eq. 6) for the chains in `list`: wavefront p of
+// a chain handles the pair (i, i+1), i = (e mod 2) + 2p.  The decision is
+// taken from the running energies when their bounds settle it, otherwise from
+// the FP64-order energies of both conformations (which also re-synchronise
+// them).
+template <int B, int W>
 __global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *__restrict__ list,
                                                  int max_pairs, int force) {
-    using G = Geo<B>;
-    __shared__ double X[G::NP], Y[G::NP], Z[G::NP];
+    using G = Geo<B, W>;
+    __shared__ double XYZ[3 * G::NP];
+    double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
     const int c = list[blockIdx.x / max_pairs];
     const int p = blockIdx.x % max_pairs;
     const int64_t t = T.te[0], e = T.te[1];
@@ -415,11 +553,13 @@ __global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *
         acc = sure_acc;
     } else {
         band = true;
-        load_replica<B>(X, Y, Z, T.coords + T.coord_off[q1]);
-        const double c1 = energy_wave<B>(X, Y, Z, n, T.k);
+        copy_replica<B, W, 64>(XYZ, T.coords + T.coord_off[q1]);
         wave_sync();
-        load_replica<B>(X, Y, Z, T.coords + T.coord_off[q2]);
-        const double c2 = energy_wave<B>(X, Y, Z, n, T.k);
+        const double c1 = energy_wave<B, W>(X, Y, Z, n, T.k);
+        wave_sync();
+        copy_replica<B, W, 64>(XYZ, T.coords + T.coord_off[q2]);
+        wave_sync();
+        const double c2 = energy_wave<B, W>(X, Y, Z, n, T.k);
         const double d = db * (c1 - c2);
         acc = (d >= 0.0) || (pl < d);
         if (threadIdx.x == 0) {
@@ -493,63 +633,64 @@ __global__ void k_selftest(const Consts k, int op, const double *x, const double
     }
 }
 
-template <int B>
-hipError_t sweep_b(bool mixed, const Tables &T, const int32_t *list, int n, hipStream_t s) {
+template <int B, int W>
+hipError_t sweep_bw(bool mixed, const Tables &T, const int32_t *list, int n, hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL((k_sweep<B, true>), dim3(n), dim3(64), 0, s, T, list);
+        hipLaunchKernelGGL((k_sweep<B, W, true>), dim3(n), dim3(64 * W), 0, s, T, list);
     else
-        hipLaunchKernelGGL((k_sweep<B, false>), dim3(n), dim3(64), 0, s, T, list);
+        hipLaunchKernelGGL((k_sweep<B, W, false>), dim3(n), dim3(64 * W), 0, s, T, list);
     return hipGetLastError();
 }
 
-template <int B>
-hipError_t energy_b(const Tables &T, const int32_t *list, int n, double *oe, double *ob, int by_slot,
-                    hipStream_t s) {
-    hipLaunchKernelGGL((k_energy<B>), dim3(n), dim3(64), 0, s, T, list, oe, ob, by_slot);
+template <int B, int W>
+hipError_t energy_bw(const Tables &T, const int32_t *list, int n, double *oe, double *ob, int by_slot,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((k_energy<B, W>), dim3(n), dim3(64), 0, s, T, list, oe, ob, by_slot);
     return hipGetLastError();
 }
 
-template <int B>
-hipError_t exchange_b(const Tables &T, const int32_t *list, int nc, int mp, int force, hipStream_t s) {
-    hipLaunchKernelGGL((k_exchange<B>), dim3(nc * mp), dim3(64), 0, s, T, list, mp, force);
+template <int B, int W>
+hipError_t exchange_bw(const Tables &T, const int32_t *list, int nc, int mp, int force, hipStream_t s) {
+    hipLaunchKernelGGL((k_exchange<B, W>), dim3(nc * mp), dim3(64), 0, s, T, list, mp, force);
     return hipGetLastError();
 }
 
 }  // namespace
 
-#define PT_DISPATCH_B(bpl, CALL)             \
-    switch (bpl) {                           \
-        case 1: return CALL(1);              \
-        case 2: return CALL(2);              \
-        case 4: return CALL(4);              \
-        case 8: return CALL(8);              \
-        case 16: return CALL(16);            \
-        case 32: return CALL(32);            \
+// The (beads per lane, wavefronts per replica) classes the library builds.
+#define PT_DISPATCH(bpl, wpr, CALL)           \
+    switch ((bpl) * 16 + (wpr)) {             \
+        case 1 * 16 + 1: return CALL(1, 1);   \
+        case 2 * 16 + 1: return CALL(2, 1);   \
+        case 4 * 16 + 1: return CALL(4, 1);   \
+        case 8 * 16 + 1: return CALL(8, 1);   \
+        case 8 * 16 + 2: return CALL(8, 2);   \
+        case 8 * 16 + 4: return CALL(8, 4);   \
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_sweep(int bpl, bool mixed, const Tables &T, const int32_t *list, int n,
+hipError_t launch_sweep(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
                         hipStream_t s) {
     if (n <= 0) return hipSuccess;
-#define PT_SW(B) sweep_b<B>(mixed, T, list, n, s)
-    PT_DISPATCH_B(bpl, PT_SW)
+#define PT_SW(B, W) sweep_bw<B, W>(mixed, T, list, n, s)
+    PT_DISPATCH(bpl, wpr, PT_SW)
 #undef PT_SW
 }
 
-hipError_t launch_energy(int bpl, const Tables &T, const int32_t *list, int n, double *out_e,
+hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *list, int n, double *out_e,
                          double *out_b, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int by_slot = (out_b == nullptr) ? 1 : 0;
-#define PT_EN(B) energy_b<B>(T, list, n, out_e, out_b, by_slot, s)
-    PT_DISPATCH_B(bpl, PT_EN)
+#define PT_EN(B, W) energy_bw<B, W>(T, list, n, out_e, out_b, by_slot, s)
+    PT_DISPATCH(bpl, wpr, PT_EN)
 #undef PT_EN
 }
 
-hipError_t launch_exchange(int bpl, const Tables &T, const int32_t *list, int n_chains,
+hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *list, int n_chains,
                            int max_pairs, int force, hipStream_t s) {
     if (n_chains <= 0 || max_pairs <= 0) return hipSuccess;
-#define PT_EX(B) exchange_b<B>(T, list, n_chains, max_pairs, force, s)
-    PT_DISPATCH_B(bpl, PT_EX)
+#define PT_EX(B, W) exchange_bw<B, W>(T, list, n_chains, max_pairs, force, s)
+    PT_DISPATCH(bpl, wpr, PT_EX)
 #undef PT_EX
 }
 

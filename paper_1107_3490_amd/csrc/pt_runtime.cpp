@@ -38,21 +38,29 @@ int fail(int code, const char *fmt, ...) {
             return fail(PT_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));             \
     } while (0)
 
-constexpr int kMaxBeads = 2048;      // 64 lanes x 32 beads per lane
+constexpr int kMaxBeads = 2048;      // 4 wavefronts x 64 lanes x 8 beads per lane
 constexpr double kSentinel = 1.0e30; // x coordinate of padding beads (far from everything)
 
-int beads_per_lane(int n) {
+// Mapping of a chain of n beads: beads per lane (a power of two <= 8) and
+// wavefronts per replica (1, 2 or 4), the smallest that cover n.
+void mapping(int n, int *bpl, int *wpr) {
     int b = 1;
-    while (64 * b < n) b <<= 1;
-    return b;
+    while (b < 8 && 64 * b < n) b <<= 1;
+    int w = 1;
+    while (64 * w * b < n) w <<= 1;
+    *bpl = b;
+    *wpr = w;
 }
+
+// Position of bead j in the swizzled layout of a (B, W) chain.
+int swizzle(int j, int B, int W) { return (j % B) * 64 * W + j / B; }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Offsets of every device array inside the caller's workspace.
 struct Layout {
     int n_chains = 0, total = 0;
-    std::vector<int> bpl;             // per chain
+    std::vector<int> bpl, wpr;        // per chain
     std::vector<int64_t> coord_off;   // per conformation (doubles)
     std::vector<int64_t> word_off;    // per slot
     int64_t coord_total = 0, words_total = 0;
@@ -131,15 +139,16 @@ Layout plan(const pt_config *c) {
     for (int ch = 0; ch < c->n_chains; ++ch) total += c->n_slots[ch];
     L.total = (int)total;
     L.bpl.resize(c->n_chains);
+    L.wpr.resize(c->n_chains);
     L.coord_off.resize(total);
     L.word_off.resize(total);
     int g = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
-        L.bpl[ch] = beads_per_lane(c->n_beads[ch]);
+        mapping(c->n_beads[ch], &L.bpl[ch], &L.wpr[ch]);
         for (int s = 0; s < c->n_slots[ch]; ++s, ++g) {
             L.coord_off[g] = L.coord_total;
             L.word_off[g] = L.words_total;
-            L.coord_total += 3 * 64 * L.bpl[ch];
+            L.coord_total += 3 * 64 * L.wpr[ch] * L.bpl[ch];
             L.words_total += (c->n_beads[ch] + 63) / 64;
         }
     }
@@ -188,7 +197,7 @@ double fene_y(const pt::Consts &k, const double *a, const double *b) {
 }  // namespace
 
 struct Class {
-    int bpl = 0;
+    int bpl = 0, wpr = 0;
     int n_slots = 0, n_chains = 0, max_pairs = 0;
     int32_t *d_slots = nullptr;   // slot (= starting conformation) list
     int32_t *d_chains = nullptr;  // chain list
@@ -215,11 +224,11 @@ namespace {
 
 int enqueue_sweep(pt_handle *h, hipStream_t s) {
     for (const Class &c : h->classes) {
-        hipError_t e = pt::launch_sweep(c.bpl, h->mixed, h->T, c.d_slots, c.n_slots, s);
+        hipError_t e = pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, s);
         if (e != hipSuccess) return fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     }
     for (const Class &c : h->classes) {
-        hipError_t e = pt::launch_exchange(c.bpl, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, s);
+        hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, s);
         if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
     }
     hipError_t e = pt::launch_advance(h->T, 0, s);
@@ -280,7 +289,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
         int g = 0;
         int64_t src = 0;
         for (int ch = 0; ch < C; ++ch) {
-            const int n = cfg->n_beads[ch], B = L.bpl[ch], NP = 64 * B;
+            const int n = cfg->n_beads[ch], B = L.bpl[ch], W = L.wpr[ch], NP = 64 * W * B;
             chain_n[ch] = n;
             chain_slots[ch] = cfg->n_slots[ch];
             chain_slot0[ch] = g;
@@ -299,7 +308,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
                         return fail(PT_EDOMAIN, "slot %d: bond (%d,%d) at or beyond r0 +- R", g, j, j + 1);
                 double *dst = coords.data() + L.coord_off[g];
                 for (int j = 0; j < NP; ++j) {
-                    const int p = ((j & (B - 1)) * 64) + j / B;
+                    const int p = swizzle(j, B, W);
                     dst[p] = (j < n) ? xyz[3 * j] : kSentinel;
                     dst[NP + p] = (j < n) ? xyz[3 * j + 1] : 0.0;
                     dst[2 * NP + p] = (j < n) ? xyz[3 * j + 2] : 0.0;
@@ -351,14 +360,15 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.k = k;
     h->d_tmp = (double *)(w + L.o_tmp);
 
-    // Classes by beads per lane.
-    std::map<int, std::vector<int>> cls_chains;
-    for (int ch = 0; ch < C; ++ch) cls_chains[L.bpl[ch]].push_back(ch);
+    // Classes by (beads per lane, wavefronts per replica).
+    std::map<std::pair<int, int>, std::vector<int>> cls_chains;
+    for (int ch = 0; ch < C; ++ch) cls_chains[{L.bpl[ch], L.wpr[ch]}].push_back(ch);
     std::vector<int32_t> lists;
     lists.reserve(L.lists_len);
     for (auto &kv : cls_chains) {
         Class cl;
-        cl.bpl = kv.first;
+        cl.bpl = kv.first.first;
+        cl.wpr = kv.first.second;
         const size_t slot_at = lists.size();
         for (int ch : kv.second)
             for (int s = 0; s < cfg->n_slots[ch]; ++s) lists.push_back(chain_slot0[ch] + s);
@@ -406,7 +416,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     if (e != hipSuccess) return fin(fail(PT_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e)));
     // Starting energies in the FP64 order; their bounds seed the running bounds.
     for (const Class &cl : h->classes) {
-        e = pt::launch_energy(cl.bpl, T, cl.d_slots, cl.n_slots, T.e_run, T.b_run, h->stream);
+        e = pt::launch_energy(cl.bpl, cl.wpr, T, cl.d_slots, cl.n_slots, T.e_run, T.b_run, h->stream);
         if (e != hipSuccess) return fin(fail(PT_EHIP, "energy launch failed: %s", hipGetErrorString(e)));
     }
     e = hipStreamSynchronize(h->stream);
@@ -445,7 +455,7 @@ PT_API int pt_sweep(pt_handle *h, int64_t n) {
 PT_API int pt_exchange(pt_handle *h) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
     for (const Class &c : h->classes) {
-        hipError_t e = pt::launch_exchange(c.bpl, h->T, c.d_chains, c.n_chains, c.max_pairs, 1, h->stream);
+        hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 1, h->stream);
         if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
     }
     hipError_t e = pt::launch_advance(h->T, 1, h->stream);
@@ -466,13 +476,13 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
     for (int64_t i = 0; i < n && rc == PT_OK; ++i) {
         for (const Class &c : h->classes) {
             PT_HIP(hipEventRecord(ev[2 * k], h->stream));
-            hipError_t e = pt::launch_sweep(c.bpl, h->mixed, h->T, c.d_slots, c.n_slots, h->stream);
+            hipError_t e = pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, h->stream);
             if (e != hipSuccess) { rc = fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e)); break; }
             PT_HIP(hipEventRecord(ev[2 * k + 1], h->stream));
             ++k;
         }
         for (const Class &c : h->classes) {
-            hipError_t e = pt::launch_exchange(c.bpl, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, h->stream);
+            hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, h->stream);
             if (e != hipSuccess) { rc = fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e)); break; }
         }
         if (rc == PT_OK) {
@@ -503,7 +513,7 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
 PT_API int pt_energy(pt_handle *h, double *h_e) {
     if (h == nullptr || h_e == nullptr) return fail(PT_EINVAL, "NULL argument");
     for (const Class &c : h->classes) {
-        hipError_t e = pt::launch_energy(c.bpl, h->T, c.d_slots, c.n_slots, h->d_tmp, nullptr, h->stream);
+        hipError_t e = pt::launch_energy(c.bpl, c.wpr, h->T, c.d_slots, c.n_slots, h->d_tmp, nullptr, h->stream);
         if (e != hipSuccess) return fail(PT_EHIP, "energy launch failed: %s", hipGetErrorString(e));
     }
     PT_HIP(hipMemcpyAsync(h_e, h->d_tmp, 8 * (size_t)h->L.total, hipMemcpyDeviceToHost, h->stream));
@@ -536,11 +546,11 @@ PT_API int pt_get_coords(pt_handle *h, double *out) {
     int g = 0;
     int64_t dst = 0;
     for (int ch = 0; ch < h->L.n_chains; ++ch) {
-        const int n = h->n_beads[ch], B = h->L.bpl[ch], NP = 64 * B;
+        const int n = h->n_beads[ch], B = h->L.bpl[ch], W = h->L.wpr[ch], NP = 64 * W * B;
         for (int s = 0; s < h->n_slots[ch]; ++s, ++g) {
             const double *src = sw.data() + h->L.coord_off[g];
             for (int j = 0; j < n; ++j) {
-                const int p = ((j & (B - 1)) * 64) + j / B;
+                const int p = swizzle(j, B, W);
                 out[dst + 3 * j] = src[p];
                 out[dst + 3 * j + 1] = src[NP + p];
                 out[dst + 3 * j + 2] = src[2 * NP + p];
@@ -584,9 +594,12 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *alog, int64_t *arows, uint8_t *el
     return PT_OK;
 }
 
-PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl) {
-    if (h == nullptr || bpl == nullptr) return fail(PT_EINVAL, "NULL argument");
-    for (int c = 0; c < h->L.n_chains; ++c) bpl[c] = h->L.bpl[c];
+PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr) {
+    if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    for (int c = 0; c < h->L.n_chains; ++c) {
+        if (bpl) bpl[c] = h->L.bpl[c];
+        if (wpr) wpr[c] = h->L.wpr[c];
+    }
     return PT_OK;
 }
 

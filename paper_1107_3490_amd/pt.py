@@ -77,7 +77,7 @@ def lib():
         L.pt_get_series.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
         L.pt_get_logs.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_int64), P(C.c_uint8), P(C.c_int64)]
         L.pt_time_sweeps.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double), P(C.c_int64)]
-        L.pt_get_mapping.argtypes = [C.c_void_p, P(C.c_int32)]
+        L.pt_get_mapping.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
         L.pt_selftest.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), C.c_int64]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_destroy.restype = None
@@ -170,10 +170,11 @@ def pt_time_sweeps(h: int, n: int):
     return sw.value, tot.value, la.value
 
 
-def pt_get_mapping(h: int, n_chains: int) -> np.ndarray:
-    out = np.zeros(n_chains, dtype=np.int32)
-    _check(lib().pt_get_mapping(C.c_void_p(h), _ptr(out, C.c_int32)))
-    return out
+def pt_get_mapping(h: int, n_chains: int):
+    bpl = np.zeros(n_chains, dtype=np.int32)
+    wpr = np.zeros(n_chains, dtype=np.int32)
+    _check(lib().pt_get_mapping(C.c_void_p(h), _ptr(bpl, C.c_int32), _ptr(wpr, C.c_int32)))
+    return bpl, wpr
 
 
 def pt_selftest(model: dict, op: int, x, y=None) -> np.ndarray:

@@ -191,12 +191,24 @@ def test_c5_chain_subset_full_size():
     assert_parity(g, o, "mixed")
 
 
-@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 129])
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 129, 512, 513, 1024, 1025, 2048])
 def test_edge_lengths(n):
+    """Ragged and exact tile sizes of every (beads per lane, wavefronts) class,
+    including the longest chain the kernels take."""
     w = I.make_workload([n], [5], [(0.2, 2.0)], "walk", 40 + n, 0, "fp64")
+    sweeps = 25 if n < 500 else 3
     for prec in ("fp64", "mixed"):
-        g, o = run_both(w, 25, prec, f"N={n}")
+        g, o = run_both(w, sweeps, prec, f"N={n}")
         assert_parity(g, o, prec)
+
+
+def test_mapping_classes():
+    pt = _pt()
+    w = I.make_workload([13, 100, 300, 500, 600, 2000], [2] * 6, [(0.3, 1.0)] * 6, "walk", 5, 0, "mixed")
+    sim = pt.Simulation(w)
+    bpl, wpr = sim.mapping()
+    sim.close()
+    assert list(bpl) == [1, 2, 8, 8, 8, 8] and list(wpr) == [1, 1, 1, 1, 2, 4]
 
 
 def test_single_slot_and_no_exchange():
