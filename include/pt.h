@@ -50,7 +50,8 @@
  *
  * Errors: every int-returning call returns PT_OK (0) or a negative code;
  * pt_last_error() gives a message (thread-local).  Asynchronous device
- * faults surface as PT_EHIP at the next call that synchronises.
+ * faults, and a persistent run whose blocks stopped waiting for each other
+ * after a timeout, surface as PT_EHIP at the next call that synchronises.
  */
 #ifndef PT_H
 #define PT_H
@@ -103,7 +104,17 @@ typedef struct pt_config {
                                        device; 0 = none                                */
     int64_t log_capacity;           /* sweeps of accept bits and exchange outcomes kept
                                        on the device; 0 = none                         */
+    int32_t schedule;               /* PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or
+                                       PT_SCHED_PERSISTENT (same results)              */
 } pt_config;
+
+/* How pt_sweep runs a class of chains (chains with the same mapping).
+ * PER_SWEEP: one sweep kernel launch per sweep, then an exchange kernel.
+ * PERSISTENT: one launch for all n sweeps; every replica stays on the chip
+ * and exchange attempts synchronise the two blocks of a pair only; used when
+ * all replicas of the class fit on the device at once (else PER_SWEEP).
+ * AUTO = PERSISTENT. */
+enum pt_schedule { PT_SCHED_AUTO = 0, PT_SCHED_PER_SWEEP = 1, PT_SCHED_PERSISTENT = 2 };
 
 typedef struct pt_handle pt_handle;
 
@@ -167,16 +178,19 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
                        uint8_t *h_exch_log, int64_t *exch_rows);
 
 /* Timing of the sweep kernels: runs n sweeps like pt_sweep, with HIP events
- * recorded on the handle's stream around every sweep-kernel launch, then
+ * recorded on the handle's stream around every sweep-kernel launch (a
+ * persistent launch covers all n sweeps and their exchange steps), then
  * synchronises.  *sweep_ms = summed sweep-kernel time, *total_ms = wall time
  * of the whole enqueue on the stream, *launches = sweep-kernel launches. */
 PT_API int pt_time_sweeps(pt_handle *h, int64_t n_sweeps, double *sweep_ms, double *total_ms,
                           int64_t *launches);
 
-/* Mapping chosen for each chain (either pointer may be NULL): beads per lane
- * (a power of two <= 8) and wavefronts per replica (1, 2 or 4), the smallest
- * pair with 64 * wpr * bpl >= N.  [n_chains] each. */
-PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_per_replica);
+/* Mapping chosen for each chain (any pointer may be NULL): beads per lane
+ * (a power of two <= 8), wavefronts per replica (1, 2 or 4), the smallest
+ * pair with 64 * wpr * bpl >= N, and 1 where the chain's class runs the
+ * persistent schedule, else 0.  [n_chains] each. */
+PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_per_replica,
+                          int32_t *persistent);
 
 /* Diagnostics of the device arithmetic (used by the test suite).  op:
  *   0: IEEE sqrt      1: IEEE x/y        2: deterministic log

@@ -44,6 +44,10 @@ struct Tables {
     const int64_t *coord_off;    // start of conformation q in coords
     double *e_run;               // running energy
     double *b_run;               // bound on |e_run - exact sum of the FP64 terms|
+    int32_t *slot_of;            // slot holding conformation q (inverse of perm)
+    int64_t *done;               // persistent runs: sweeps completed by conformation q
+    int64_t *dec;                // persistent runs: exchange steps decided for q's pair
+    int32_t *err;                // persistent runs: nonzero after a synchronisation timeout
     // per chain c
     const int32_t *chain_n;      // beads
     const int32_t *chain_slots;  // slots
@@ -74,6 +78,13 @@ hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *conf_
 hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *chain_list, int n_chains,
                            int max_pairs, int force, hipStream_t s);
 hipError_t launch_advance(const Tables &T, int force, hipStream_t s);
+// Persistent run of n_sweeps sweeps and exchange steps for one class (all of
+// its slots co-resident: cooperative launch).  *fits = 0 (and nothing is
+// launched) when the class does not fit on the device at once.
+hipError_t launch_run(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *conf_list,
+                      int n_items, int64_t n_sweeps, int64_t t0, int64_t e0, int *fits,
+                      hipStream_t s);
+hipError_t launch_set_te(const Tables &T, int64_t t, int64_t e, hipStream_t s);
 hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y,
                            double *out, int64_t n, hipStream_t s);
 

@@ -94,8 +94,8 @@ __device__ __forceinline__ void tree_push(double (&stk)[LEVELS + 1], int idx, do
     }
 }
 
-// Pairwise tree over the 64 leaves j = j0 .. j0+63 of row i (zero unless
-// i < j < n), computed in registers from LDS broadcasts.
+// Pairwise tree over the leaves j = j0 + LO .. j0 + HI - 1 of row i (zero
+// unless i < j < n), computed in registers from broadcast loads.
 template <int B, int W, int LO, int HI>
 __device__ __forceinline__ double row_chunk(const double *X, const double *Y, const double *Z,
                                             const Consts &k, int i, int n, int j0, double xi,
@@ -113,19 +113,23 @@ __device__ __forceinline__ double row_chunk(const double *X, const double *Y, co
     }
 }
 
-// FP64-order energy E(C) of Eq. (4) for the replica in LDS, on one wavefront
-// (lanes 0..63 of the calling block).  The rows are taken in aligned blocks of
-// 64: lane l computes row 64 r + l, each row being the tree over j in chunks
-// of 64 (static trees chained by a binary counter; chunks left of the block
-// or past the chain end are exact zeros and are skipped); the butterfly over
-// lanes gives the tree over the block's 64 rows, and a binary counter over r
-// the tree over all NP rows.  Bonds: contiguous lane blocks and the butterfly.
+// FP64-order energy E(C) of Eq. (4) of a replica stored in the swizzled layout
+// (LDS or HBM), on one wavefront (lanes 0..63 of the calling block).  The rows
+// are taken in aligned blocks of 64: lane l computes row 64 r + l, each row
+// being the tree over j in chunks of 16 (static trees chained by a binary
+// counter; chunks left of the block or past the chain end are exact zeros and
+// are skipped); the butterfly over lanes gives the tree over the block's 64
+// rows, and a binary counter over r the tree over all NP rows.  Bonds:
+// contiguous lane blocks and the butterfly.
 template <int B, int W>
 __device__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
                               const Consts &k) {
     using G = Geo<B, W>;
-    constexpr int BP = B * W;  // 64-row blocks = 64-leaf chunks per row
+    constexpr int BP = B * W;        // 64-row blocks
     constexpr int LC = ilog2(BP);
+    constexpr int CW = 16;           // leaves per chunk
+    constexpr int NC = G::NP / CW;   // chunks per row
+    constexpr int LR = ilog2(NC);
     const int lane = threadIdx.x & 63;
     double blk[LC + 1];
 #pragma unroll
@@ -136,15 +140,16 @@ __device__ double energy_wave(const double *X, const double *Y, const double *Z,
             const int i = r * 64 + lane;
             const int ai = G::pos(i);
             const double xi = X[ai], yi = Y[ai], zi = Z[ai];
-            double row[LC + 1];
+            double row[LR + 1];
 #pragma unroll
-            for (int l = 0; l <= LC; ++l) row[l] = 0.0;
-            for (int c = 0; c < BP; ++c) {
+            for (int l = 0; l <= LR; ++l) row[l] = 0.0;
+            for (int c = 0; c < NC; ++c) {
                 double v = 0.0;
-                if (c >= r && c * 64 < n) v = row_chunk<B, W, 0, 64>(X, Y, Z, k, i, n, c * 64, xi, yi, zi);
-                tree_push<LC>(row, c, v);
+                if (c * CW + CW > r * 64 && c * CW < n)
+                    v = row_chunk<B, W, 0, CW>(X, Y, Z, k, i, n, c * CW, xi, yi, zi);
+                tree_push<LR>(row, c, v);
             }
-            bv = wave_tree(row[LC]);
+            bv = wave_tree(row[LR]);
         }
         tree_push<LC>(blk, r, bv);
     }
@@ -216,49 +221,38 @@ __device__ __forceinline__ double tree_w(const double *v) {
     else return (v[0] + v[1]) + (v[2] + v[3]);
 }
 
-// One sweep (N attempted moves, Sec. 3.2) of every slot in `list`, then the
-// per-sweep record of E, Ree^2 and Rg^2 (Eq. 8).
-//
-// Moves are processed in batches.  A vector prologue (wavefront 0, one move
-// per lane) computes the Philox draws, -log u, the gather of r_k and of its
-// bond neighbours, the four bond terms and the conflict mask.  The serial part
-// of a move is then the pair loop over the lane's beads in registers, the
-// butterflies, one barrier to combine the W wavefront sums (W > 1), and the
-// decision, taken identically by every wavefront.
+// LDS of a sweep block: the replica mirror, the batch's move records and the
+// per-wavefront partial sums (double-buffered over consecutive moves).
+template <int B, int W>
+struct SweepLds {
+    static constexpr int MB = (W >= 4) ? 32 : 64;  // moves per batch (LDS budget at W = 4)
+    double xyz[3 * Geo<B, W>::NP];
+    MoveRec rec[MB];
+    double part[2][2][W];
+    double partx[2][W];
+    double bcast[4];
+};
+
+// The N moves of one sweep of the replica held by the block (Sec. 3.2), on
+// slot g at sweep t.  Moves are processed in batches.  A vector prologue
+// (wavefront 0, one move per lane) computes the Philox draws, -log u, the
+// gather of r_k and of its bond neighbours, the four bond terms and the
+// conflict mask.  The serial part of a move is the pair loop over the lane's
+// beads in registers, the butterflies, one barrier to combine the W wavefront
+// sums (W > 1), and the decision, taken identically by every wavefront.
 template <int B, int W, bool MIXED>
-__global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
+__device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, double (&rx)[B],
+                                            double (&ry)[B], double (&rz)[B], int g, int n,
+                                            uint32_t t, int64_t t64, double &E, double &Bd,
+                                            int64_t &n_acc, int64_t &n_rescore) {
     using G = Geo<B, W>;
-    constexpr int NT = G::NT;
-    constexpr int MB = (W >= 4) ? 32 : 64;  // moves per batch (LDS budget at W = 4)
-    __shared__ double XYZ[3 * G::NP];
-    double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
-    __shared__ MoveRec rec[MB];
-    __shared__ double part[2][2][W];
-    __shared__ double partx[2][W];
+    constexpr int MB = SweepLds<B, W>::MB;
+    double *const X = S.xyz, *const Y = S.xyz + G::NP, *const Z = S.xyz + 2 * G::NP;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const Consts &K = T.k;
-    const int g = list[blockIdx.x];
-    const int c = T.slot_chain[g];
-    const int n = T.chain_n[c];
     const double beta = T.beta[g];
     const uint32_t gid = T.slot_gid[g];
-    const int64_t t64 = T.te[0];
-    const uint32_t t = (uint32_t)t64;
-    const int q = T.perm[g];
-    double *cq = T.coords + T.coord_off[q];
-    copy_replica<B, W, NT>(XYZ, cq);
-    __syncthreads();
-    double rx[B], ry[B], rz[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        rx[b] = X[b * NT + tid];
-        ry[b] = Y[b * NT + tid];
-        rz[b] = Z[b * NT + tid];
-    }
-
-    double E = T.e_run[q], Bd = T.b_run[q];
-    int64_t n_acc = 0, n_rescore = 0;
     uint64_t *logrow = (T.accept_log != nullptr && t64 < T.log_cap)
                            ? T.accept_log + t64 * T.words_total + T.word_off[g]
                            : nullptr;
@@ -300,7 +294,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
             }
             r.conflict = cm;
             r.pad = 0;
-            if (lane < MB) rec[lane] = r;
+            if (lane < MB) S.rec[lane] = r;
         }
         __syncthreads();
         const int nb = (n - m0 < MB) ? (n - m0) : MB;
@@ -310,7 +304,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
         int last_k = -1;
         double lx = 0.0, ly = 0.0, lz = 0.0;
         for (int i = 0; i < nb; ++i) {
-            const MoveRec r = rec[i];
+            const MoveRec r = S.rec[i];
             const int k = __builtin_amdgcn_readfirstlane(r.k);
             const uint64_t cf =
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r.conflict)) |
@@ -372,12 +366,12 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
                 double bsum = (double)wave_tree(s.b);
                 if constexpr (W > 1) {
                     if (lane == 0) {
-                        part[i & 1][0][wv] = sm;
-                        part[i & 1][1][wv] = bsum;
+                        S.part[i & 1][0][wv] = sm;
+                        S.part[i & 1][1][wv] = bsum;
                     }
                     __syncthreads();
-                    sm = tree_w<W>(part[i & 1][0]);
-                    bsum = tree_w<W>(part[i & 1][1]);
+                    sm = tree_w<W>(S.part[i & 1][0]);
+                    bsum = tree_w<W>(S.part[i & 1][1]);
                 }
                 const double bs = K.kbound * bsum;
                 const double dem = sm + df;
@@ -401,8 +395,8 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
                 double sc = wave_tree(s.t);
                 double ab = wave_tree(s.a);
                 if constexpr (W > 1) {
-                    double *pp = MIXED ? partx[0] : part[i & 1][0];
-                    double *pa = MIXED ? partx[1] : part[i & 1][1];
+                    double *pp = MIXED ? S.partx[0] : S.part[i & 1][0];
+                    double *pa = MIXED ? S.partx[1] : S.part[i & 1][1];
                     if (lane == 0) {
                         pp[wv] = sc;
                         pa[wv] = ab;
@@ -448,14 +442,24 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
             logrow[m0 >> 6] = logword;
         if (((m0 + MB) & 63) == 0) logword = 0;
     }
-
-    // Write the replica back; record the sweep (before any exchange); re-sync
-    // the running energy with the FP64-order energy when its bound has grown past
-    // resync_rel of max(1, |E|) (a start with near-overlapping beads, or many
-    // accepted moves).
     __syncthreads();
-    copy_replica<B, W, NT>(cq, XYZ);
-    if (wv == 0) {
+}
+
+// The per-sweep record of slot g (before any exchange): E, Ree^2 and Rg^2
+// (Eq. 8) into the accumulators and the series; the running energy of
+// conformation q.  The running energy is first replaced by the FP64-order
+// energy when its bound has grown past resync_rel of max(1, |E|) (a start
+// with near-overlapping beads, or many accepted moves).  Wavefront 0 does the
+// work; E and Bd leave valid in every thread.
+template <int B, int W>
+__device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S, int g, int q,
+                                             int n, int64_t t64, double &E, double &Bd,
+                                             int64_t n_acc, int64_t n_rescore) {
+    using G = Geo<B, W>;
+    const double *X = S.xyz, *Y = S.xyz + G::NP, *Z = S.xyz + 2 * G::NP;
+    const Consts &K = T.k;
+    const int tid = threadIdx.x;
+    if (tid < 64) {
         double ree2, rg2;
         shape_wave<B, W>(X, Y, Z, n, ree2, rg2);
         bool resync = false;
@@ -464,9 +468,11 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
             Bd = bound_energy(K, G::LOG_NP, n, E, 0.0);
             resync = true;
         }
-        if (lane == 0) {
+        if (tid == 0) {
             T.e_run[q] = E;
             T.b_run[q] = Bd;
+            S.bcast[0] = E;
+            S.bcast[1] = Bd;
             int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
             cnt[0] += n_acc;
             cnt[3] += n_rescore;
@@ -486,6 +492,46 @@ __global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t 
             }
         }
     }
+    if constexpr (W > 1) {
+        __syncthreads();
+        E = S.bcast[0];
+        Bd = S.bcast[1];
+    }
+}
+
+template <int B, int W>
+__device__ __forceinline__ void load_regs(const SweepLds<B, W> &S, double (&rx)[B], double (&ry)[B],
+                                          double (&rz)[B]) {
+    using G = Geo<B, W>;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        rx[b] = S.xyz[b * G::NT + tid];
+        ry[b] = S.xyz[G::NP + b * G::NT + tid];
+        rz[b] = S.xyz[2 * G::NP + b * G::NT + tid];
+    }
+}
+
+// One sweep of every slot in `list` (one block per slot), then its record.
+template <int B, int W, bool MIXED>
+__global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
+    using G = Geo<B, W>;
+    __shared__ SweepLds<B, W> S;
+    const int g = list[blockIdx.x];
+    const int c = T.slot_chain[g];
+    const int n = T.chain_n[c];
+    const int64_t t64 = T.te[0];
+    const int q = T.perm[g];
+    double *cq = T.coords + T.coord_off[q];
+    copy_replica<B, W, G::NT>(S.xyz, cq);
+    __syncthreads();
+    double rx[B], ry[B], rz[B];
+    load_regs<B, W>(S, rx, ry, rz);
+    double E = T.e_run[q], Bd = T.b_run[q];
+    int64_t n_acc = 0, n_rescore = 0;
+    sweep_moves<B, W, MIXED>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
+    copy_replica<B, W, G::NT>(cq, S.xyz);
+    sweep_record<B, W>(T, S, g, q, n, t64, E, Bd, n_acc, n_rescore);
 }
 
 // ----------------------------------------------------------------- energy --
@@ -511,17 +557,65 @@ __global__ __launch_bounds__(64) void k_energy(const Tables T, const int32_t *__
 }
 
 // --------------------------------------------------------------- exchange --
-// One exchange step (Sec. 3.3, Eq. 6) for the chains in `list`: wavefront p of
-// a chain handles the pair (i, i+1), i = (e mod 2) + 2p.  The decision is
-// taken from the running energies when their bounds settle it, otherwise from
-// the FP64-order energies of both conformations (which also re-synchronise
-// them).
+// Decision of one exchange attempt (Sec. 3.3, Eq. 6) between slots (g, g+1)
+// of chain c at exchange step e, holding conformations q1, q2 with running
+// energies e1, e2 and bounds b1, b2.  The decision is taken from the running
+// energies when their bounds settle it; otherwise canon(0), canon(1) give the
+// FP64-order energies of q1 and q2, the decision is exact, and e1, b1, e2, b2
+// are replaced by those energies and their bounds (band = true).  Wavefront-
+// uniform; called by one wavefront.
+template <int B, int W, class Canon>
+__device__ __forceinline__ bool exch_decide(const Tables &T, int c, int i, int64_t e, int n, int g,
+                                            double &e1, double &bb1, double &e2, double &bb2,
+                                            bool &band, const Canon &canon) {
+    using G = Geo<B, W>;
+    const double db = T.beta[g] - T.beta[g + 1];
+    const U4 w = philox10(U4{(uint32_t)i, (uint32_t)e, T.chain_sid[c], 2u}, T.seed);
+    const double pl = det_log(unit_open(w.x));
+    const double dd = e1 - e2;
+    const double tot = (bb1 + bound_energy(T.k, G::LOG_NP, n, e1, bb1) + bb2 +
+                        bound_energy(T.k, G::LOG_NP, n, e2, bb2)) * (1.0 + 0x1p-20) +
+                       0x1p-50 * dabs(dd);
+    const double d1 = db * (dd - tot), d2 = db * (dd + tot);
+    const double dlo = (d1 < d2) ? d1 : d2, dhi = (d1 < d2) ? d2 : d1;
+    const bool sure_acc = (dlo >= 0.0) || (pl < dlo);
+    const bool sure_rej = (dhi < 0.0) && !(pl < dhi);
+    band = false;
+    if (finite(tot) && finite(dd) && finite(db) && (sure_acc || sure_rej)) return sure_acc;
+    band = true;
+    const double c1 = canon(0);
+    const double c2 = canon(1);
+    const double d = db * (c1 - c2);
+    e1 = c1;
+    bb1 = bound_energy(T.k, G::LOG_NP, n, c1, 0.0);
+    e2 = c2;
+    bb2 = bound_energy(T.k, G::LOG_NP, n, c2, 0.0);
+    return (d >= 0.0) || (pl < d);
+}
+
+// Book-keeping of a decided attempt (thread 0): counters, log, permutation.
+__device__ __forceinline__ void exch_commit(const Tables &T, int g, int64_t e, int q1, int q2, bool acc,
+                                            bool band) {
+    int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
+    cnt[1] += 1;
+    if (band) cnt[4] += 1;
+    if (acc) {
+        cnt[2] += 1;
+        T.perm[g] = q2;
+        T.perm[g + 1] = q1;
+        T.slot_of[q1] = g + 1;
+        T.slot_of[q2] = g;
+    }
+    if (T.exch_log != nullptr && e < T.log_cap) T.exch_log[e * T.total_slots + g] = acc ? 1 : 0;
+}
+
+// One exchange step for the chains in `list`: wavefront p of a chain handles
+// the pair (i, i+1), i = (e mod 2) + 2p.
 template <int B, int W>
 __global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *__restrict__ list,
                                                  int max_pairs, int force) {
     using G = Geo<B, W>;
     __shared__ double XYZ[3 * G::NP];
-    double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
     const int c = list[blockIdx.x / max_pairs];
     const int p = blockIdx.x % max_pairs;
     const int64_t t = T.te[0], e = T.te[1];
@@ -533,53 +627,159 @@ __global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *
     const int g = T.chain_slot0[c] + i;
     const int n = T.chain_n[c];
     const int q1 = T.perm[g], q2 = T.perm[g + 1];
-    const double b1 = T.beta[g], b2 = T.beta[g + 1];
-    const U4 w = philox10(U4{(uint32_t)i, (uint32_t)e, T.chain_sid[c], 2u}, T.seed);
-    const double pl = det_log(unit_open(w.x));
-    const double e1 = T.e_run[q1], e2 = T.e_run[q2];
-    const double bb1 = T.b_run[q1], bb2 = T.b_run[q2];
-    const double db = b1 - b2;
-    const double dd = e1 - e2;
-    const double tot = (bb1 + bound_energy(T.k, G::LOG_NP, n, e1, bb1) + bb2 +
-                        bound_energy(T.k, G::LOG_NP, n, e2, bb2)) * (1.0 + 0x1p-20) +
-                       0x1p-50 * dabs(dd);
-    const double d1 = db * (dd - tot), d2 = db * (dd + tot);
-    const double dlo = (d1 < d2) ? d1 : d2, dhi = (d1 < d2) ? d2 : d1;
-    const bool sure_acc = (dlo >= 0.0) || (pl < dlo);
-    const bool sure_rej = (dhi < 0.0) && !(pl < dhi);
-    bool acc;
+    double e1 = T.e_run[q1], e2 = T.e_run[q2];
+    double bb1 = T.b_run[q1], bb2 = T.b_run[q2];
     bool band = false;
-    if (finite(tot) && finite(dd) && finite(db) && (sure_acc || sure_rej)) {
-        acc = sure_acc;
-    } else {
-        band = true;
-        copy_replica<B, W, 64>(XYZ, T.coords + T.coord_off[q1]);
+    // Captures by value: a reference to the kernel argument T would force a
+    // copy of it into scratch memory.
+    const double *src1 = T.coords + T.coord_off[q1], *src2 = T.coords + T.coord_off[q2];
+    const Consts K = T.k;
+    double *const lds = XYZ;
+    auto canon = [lds, src1, src2, n, K](int which) {
         wave_sync();
-        const double c1 = energy_wave<B, W>(X, Y, Z, n, T.k);
+        copy_replica<B, W, 64>(lds, which == 0 ? src1 : src2);
         wave_sync();
-        copy_replica<B, W, 64>(XYZ, T.coords + T.coord_off[q2]);
-        wave_sync();
-        const double c2 = energy_wave<B, W>(X, Y, Z, n, T.k);
-        const double d = db * (c1 - c2);
-        acc = (d >= 0.0) || (pl < d);
-        if (threadIdx.x == 0) {
-            T.e_run[q1] = c1;
-            T.b_run[q1] = bound_energy(T.k, G::LOG_NP, n, c1, 0.0);
-            T.e_run[q2] = c2;
-            T.b_run[q2] = bound_energy(T.k, G::LOG_NP, n, c2, 0.0);
-        }
-    }
+        return energy_wave<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K);
+    };
+    const bool acc = exch_decide<B, W>(T, c, i, e, n, g, e1, bb1, e2, bb2, band, canon);
     if (threadIdx.x == 0) {
-        int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
-        cnt[1] += 1;
-        if (band) cnt[4] += 1;
-        if (acc) {
-            cnt[2] += 1;
-            T.perm[g] = q2;
-            T.perm[g + 1] = q1;
+        if (band) {
+            T.e_run[q1] = e1;
+            T.b_run[q1] = bb1;
+            T.e_run[q2] = e2;
+            T.b_run[q2] = bb2;
         }
-        if (T.exch_log != nullptr && e < T.log_cap) T.exch_log[e * T.total_slots + g] = acc ? 1 : 0;
+        exch_commit(T, g, e, q1, q2, acc, band);
     }
+}
+
+// ---------------------------------------------------------- persistent run --
+// Spin (one thread) until *p >= v; false after a timeout or when another block
+// reported one, which also ends the waiting of every other block.
+__device__ __forceinline__ bool wait_ge(const int64_t *p, int64_t v, int32_t *err) {
+    for (uint32_t it = 0; it < (1u << 24); ++it) {
+        if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+}
+
+// n_sweeps sweeps and exchange steps of every conformation in `list`, one
+// block per conformation, all blocks resident at once (cooperative launch).
+// A block keeps its replica in LDS and registers for the whole run and
+// follows it from slot to slot.  Exchange attempts synchronise pairs only:
+// after a sweep that is followed by an exchange step, the holder of slot g
+// publishes its running energy, coordinates and conformation id and sets
+// done[g] = t + 1; the holder of the lower slot of an attempted pair waits for
+// its partner's flag, decides exactly as k_exchange does, writes the new slot
+// assignment and sets dec[g+1] = t + 1, which the partner waits for.
+template <int B, int W, bool MIXED>
+__global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *__restrict__ list,
+                                                int64_t n_sweeps, int64_t t0, int64_t e0) {
+    using G = Geo<B, W>;
+    __shared__ SweepLds<B, W> S;
+    __shared__ int32_t s_slot, s_ok;
+    const int tid = threadIdx.x;
+    const int q = list[blockIdx.x];
+    const int c = T.slot_chain[q];
+    const int n = T.chain_n[c];
+    const int R = T.chain_slots[c];
+    const int s0 = T.chain_slot0[c];
+    double *cq = T.coords + T.coord_off[q];
+    copy_replica<B, W, G::NT>(S.xyz, cq);
+    __syncthreads();
+    double rx[B], ry[B], rz[B];
+    load_regs<B, W>(S, rx, ry, rz);
+    double E = T.e_run[q], Bd = T.b_run[q];
+    int g = T.slot_of[q];
+    int64_t e = e0;
+    for (int64_t s = 0; s < n_sweeps; ++s) {
+        const int64_t t64 = t0 + s;
+        int64_t n_acc = 0, n_rescore = 0;
+        sweep_moves<B, W, MIXED>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
+        sweep_record<B, W>(T, S, g, q, n, t64, E, Bd, n_acc, n_rescore);
+        if (!(T.exchange_every > 0 && (t64 + 1) % T.exchange_every == 0)) continue;
+        // Publish this conformation at slot g.
+        copy_replica<B, W, G::NT>(cq, S.xyz);
+        if (tid == 0) T.perm[g] = q;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&T.done[g], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int i = g - s0;
+        const int par = (int)(e & 1);
+        const bool lower = i >= par && ((i - par) & 1) == 0 && i + 1 < R;
+        const bool upper = i >= 1 + par && ((i - 1 - par) & 1) == 0;
+        if (tid < 64) {
+            int32_t ok = 1, slot = g;
+            if (lower) {
+                if (tid == 0) ok = wait_ge(&T.done[g + 1], t64 + 1, T.err) ? 1 : 0;
+                ok = __builtin_amdgcn_readfirstlane(ok);
+                if (ok) {
+                    __threadfence();
+                    const int q2 = T.perm[g + 1];
+                    double e1 = E, bb1 = Bd;
+                    double e2 = T.e_run[q2], bb2 = T.b_run[q2];
+                    bool band = false;
+                    const double *c2 = T.coords + T.coord_off[q2];
+                    const double *c1 = S.xyz;
+                    const Consts K = T.k;
+                    auto canon = [c1, c2, n, K](int which) {
+                        const double *p = which == 0 ? c1 : c2;
+                        return energy_wave<B, W>(p, p + G::NP, p + 2 * G::NP, n, K);
+                    };
+                    const bool acc = exch_decide<B, W>(T, c, i, e, n, g, e1, bb1, e2, bb2, band, canon);
+                    if (tid == 0) {
+                        if (band) {
+                            T.e_run[q] = e1;
+                            T.b_run[q] = bb1;
+                            T.e_run[q2] = e2;
+                            T.b_run[q2] = bb2;
+                            S.bcast[0] = e1;
+                            S.bcast[1] = bb1;
+                        } else {
+                            S.bcast[0] = E;
+                            S.bcast[1] = Bd;
+                        }
+                        exch_commit(T, g, e, q, q2, acc, band);
+                        __threadfence();
+                        __hip_atomic_store(&T.dec[g + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    slot = acc ? g + 1 : g;
+                }
+            } else if (upper) {
+                if (tid == 0) ok = wait_ge(&T.dec[g], t64 + 1, T.err) ? 1 : 0;
+                ok = __builtin_amdgcn_readfirstlane(ok);
+                if (ok) {
+                    __threadfence();
+                    if (tid == 0) {
+                        S.bcast[0] = T.e_run[q];
+                        S.bcast[1] = T.b_run[q];
+                    }
+                    slot = T.slot_of[q];
+                }
+            } else if (tid == 0) {
+                S.bcast[0] = E;
+                S.bcast[1] = Bd;
+            }
+            if (tid == 0) {
+                s_slot = slot;
+                s_ok = ok;
+            }
+        }
+        __syncthreads();
+        if (!s_ok) return;  // a partner never arrived: the error flag is set
+        g = s_slot;
+        E = S.bcast[0];
+        Bd = S.bcast[1];
+        e += 1;
+        __syncthreads();
+        // The LDS copy is current: reloading keeps the register copy dead
+        // across the exchange step, which has register needs of its own.
+        load_regs<B, W>(S, rx, ry, rz);
+    }
+    copy_replica<B, W, G::NT>(cq, S.xyz);
 }
 
 // Advance the run counters after a sweep (t += 1, and e += 1 when an exchange
@@ -594,6 +794,15 @@ __global__ void k_advance(const Tables T, int exchange_only) {
     const bool due = T.exchange_every > 0 && (t + 1) % T.exchange_every == 0;
     T.te[0] = t + 1;
     if (due) T.te[1] += 1;
+}
+
+// Set the run counters (after persistent runs, whose kernels take them as
+// arguments).
+__global__ void k_set_te(const Tables T, int64_t t, int64_t e) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        T.te[0] = t;
+        T.te[1] = e;
+    }
 }
 
 // --------------------------------------------------------------- selftest --
@@ -655,6 +864,24 @@ hipError_t exchange_bw(const Tables &T, const int32_t *list, int nc, int mp, int
     return hipGetLastError();
 }
 
+template <int B, int W>
+hipError_t run_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64_t n_sweeps,
+                  int64_t t0, int64_t e0, int *fits, hipStream_t s) {
+    const void *f = mixed ? (const void *)k_run<B, W, true> : (const void *)k_run<B, W, false>;
+    int per_cu = 0, dev = 0, cus = 0, coop = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, 0);
+    if (err != hipSuccess) return err;
+    *fits = (coop != 0 && (int64_t)per_cu * cus >= n) ? 1 : 0;
+    if (!*fits || n <= 0 || n_sweeps <= 0) return hipSuccess;  // n_sweeps = 0: query only
+    Tables tt = T;
+    const int32_t *ll = list;
+    void *args[] = {(void *)&tt, (void *)&ll, (void *)&n_sweeps, (void *)&t0, (void *)&e0};
+    return hipLaunchCooperativeKernel(f, dim3(n), dim3(64 * W), args, 0, s);
+}
+
 }  // namespace
 
 // The (beads per lane, wavefronts per replica) classes the library builds.
@@ -694,8 +921,20 @@ hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *lis
 #undef PT_EX
 }
 
+hipError_t launch_run(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
+                      int64_t n_sweeps, int64_t t0, int64_t e0, int *fits, hipStream_t s) {
+#define PT_RUN(B, W) run_bw<B, W>(mixed, T, list, n, n_sweeps, t0, e0, fits, s)
+    PT_DISPATCH(bpl, wpr, PT_RUN)
+#undef PT_RUN
+}
+
 hipError_t launch_advance(const Tables &T, int exchange_only, hipStream_t s) {
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, T, exchange_only);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_te(const Tables &T, int64_t t, int64_t e, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_te, dim3(1), dim3(64), 0, s, T, t, e);
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ struct Layout {
     std::vector<int64_t> word_off;    // per slot
     int64_t coord_total = 0, words_total = 0;
     size_t o_slot_chain, o_slot_index, o_slot_gid, o_beta, o_perm, o_acc, o_counts, o_word_off;
-    size_t o_coord_off, o_e_run, o_b_run, o_coords;
+    size_t o_coord_off, o_e_run, o_b_run, o_coords, o_slot_of, o_done, o_dec, o_err;
     size_t o_chain_n, o_chain_slots, o_chain_slot0, o_chain_sid;
     size_t o_te, o_lists, o_tmp, o_alog, o_elog, o_series;
     size_t bytes = 0;
@@ -86,6 +86,8 @@ int validate(const pt_model *m, const pt_config *c) {
     if (c->precision != PT_FP64 && c->precision != PT_MIXED) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_MIXED");
     if (c->exchange_every < 0) return fail(PT_EINVAL, "exchange_every must be >= 0");
     if (c->series_capacity < 0 || c->log_capacity < 0) return fail(PT_EINVAL, "capacities must be >= 0");
+    if (c->schedule < PT_SCHED_AUTO || c->schedule > PT_SCHED_PERSISTENT)
+        return fail(PT_EINVAL, "schedule must be PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or PT_SCHED_PERSISTENT");
     int64_t total = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
         if (c->n_beads[ch] < 2) return fail(PT_EINVAL, "chain %d: n_beads must be >= 2", ch);
@@ -171,6 +173,10 @@ Layout plan(const pt_config *c) {
     L.o_e_run = take(8 * S);
     L.o_b_run = take(8 * S);
     L.o_coords = take(8 * (size_t)L.coord_total);
+    L.o_slot_of = take(4 * S);
+    L.o_done = take(8 * S);
+    L.o_dec = take(8 * S);
+    L.o_err = take(16);
     L.o_chain_n = take(4 * C);
     L.o_chain_slots = take(4 * C);
     L.o_chain_slot0 = take(4 * C);
@@ -198,6 +204,7 @@ double fene_y(const pt::Consts &k, const double *a, const double *b) {
 
 struct Class {
     int bpl = 0, wpr = 0;
+    bool persistent = false;  // whole sweeps run by one cooperative launch
     int n_slots = 0, n_chains = 0, max_pairs = 0;
     int32_t *d_slots = nullptr;   // slot (= starting conformation) list
     int32_t *d_chains = nullptr;  // chain list
@@ -224,10 +231,12 @@ namespace {
 
 int enqueue_sweep(pt_handle *h, hipStream_t s) {
     for (const Class &c : h->classes) {
+        if (c.persistent) continue;
         hipError_t e = pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, s);
         if (e != hipSuccess) return fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     }
     for (const Class &c : h->classes) {
+        if (c.persistent) continue;
         hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, s);
         if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
     }
@@ -348,6 +357,10 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.chain_slot0 = (const int32_t *)(w + L.o_chain_slot0);
     T.chain_sid = (const uint32_t *)(w + L.o_chain_sid);
     T.te = (int64_t *)(w + L.o_te);
+    T.slot_of = (int32_t *)(w + L.o_slot_of);
+    T.done = (int64_t *)(w + L.o_done);
+    T.dec = (int64_t *)(w + L.o_dec);
+    T.err = (int32_t *)(w + L.o_err);
     T.accept_log = L.log_cap > 0 ? (uint64_t *)(w + L.o_alog) : nullptr;
     T.log_cap = L.log_cap;
     T.words_total = L.words_total;
@@ -408,8 +421,12 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     PT_UP(L.o_chain_sid, chain_sid);
     PT_UP(L.o_te, te);
     PT_UP(L.o_lists, lists);
+    PT_UP(L.o_slot_of, perm);
 #undef PT_UP
     hipError_t e = hipMemsetAsync(w + L.o_acc, 0, 8 * 5 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_done, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_dec, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_err, 0, 16, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_counts, 0, 8 * pt::PT_NCOUNTS * (size_t)S, h->stream);
     if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_elog, 0xFF, (size_t)S * L.log_cap, h->stream);
     if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_alog, 0, 8 * (size_t)L.words_total * L.log_cap, h->stream);
@@ -421,34 +438,74 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     }
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "initialisation failed: %s", hipGetErrorString(e)));
+    // Persistent schedule for every class whose replicas fit on the device at once.
+    if (cfg->schedule != PT_SCHED_PER_SWEEP) {
+        for (Class &cl : h->classes) {
+            int fits = 0;
+            e = pt::launch_run(cl.bpl, cl.wpr, h->mixed, T, cl.d_slots, cl.n_slots, 0, 0, 0, &fits, h->stream);
+            if (e != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e)));
+            cl.persistent = fits != 0;
+        }
+    }
     e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)));
     *out = h;
     return PT_OK;
 }
 
+// Persistent classes: one cooperative launch each covers all n sweeps,
+// exchanges included.  With ev, brackets every launch with an event pair.
+int enqueue_persistent(pt_handle *h, int64_t n, std::vector<hipEvent_t> *ev, size_t *k) {
+    for (const Class &c : h->classes) {
+        if (!c.persistent) continue;
+        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k], h->stream));
+        int fits = 0;
+        hipError_t e = pt::launch_run(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, h->t_host,
+                                      h->e_host, &fits, h->stream);
+        if (e != hipSuccess) return fail(PT_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
+        if (!fits) return fail(PT_EHIP, "persistent class no longer fits on the device");
+        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k + 1], h->stream));
+        if (k) ++*k;
+    }
+    return PT_OK;
+}
+
+bool any_per_sweep(const pt_handle *h) {
+    for (const Class &c : h->classes)
+        if (!c.persistent) return true;
+    return false;
+}
+
 PT_API int pt_sweep(pt_handle *h, int64_t n) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
     if (n == 0) return PT_OK;
-    if (n >= 16 && h->graph16 == nullptr) {
-        int rc = capture(h, 16, &h->graph16);
-        if (rc != PT_OK) return rc;
+    int rc = enqueue_persistent(h, n, nullptr, nullptr);
+    if (rc != PT_OK) return rc;
+    if (any_per_sweep(h)) {
+        if (n >= 16 && h->graph16 == nullptr) {
+            rc = capture(h, 16, &h->graph16);
+            if (rc != PT_OK) return rc;
+        }
+        if (h->graph1 == nullptr) {
+            rc = capture(h, 1, &h->graph1);
+            if (rc != PT_OK) return rc;
+        }
+        int64_t left = n;
+        while (left >= 16) {
+            PT_HIP(hipGraphLaunch(h->graph16, h->stream));
+            left -= 16;
+        }
+        while (left > 0) {
+            PT_HIP(hipGraphLaunch(h->graph1, h->stream));
+            left -= 1;
+        }
+        advance_host(h, n);
+    } else {
+        advance_host(h, n);
+        hipError_t e = pt::launch_set_te(h->T, h->t_host, h->e_host, h->stream);
+        if (e != hipSuccess) return fail(PT_EHIP, "counter update failed: %s", hipGetErrorString(e));
     }
-    if (h->graph1 == nullptr) {
-        int rc = capture(h, 1, &h->graph1);
-        if (rc != PT_OK) return rc;
-    }
-    int64_t left = n;
-    while (left >= 16) {
-        PT_HIP(hipGraphLaunch(h->graph16, h->stream));
-        left -= 16;
-    }
-    while (left > 0) {
-        PT_HIP(hipGraphLaunch(h->graph1, h->stream));
-        left -= 1;
-    }
-    advance_host(h, n);
     return PT_OK;
 }
 
@@ -467,14 +524,18 @@ PT_API int pt_exchange(pt_handle *h) {
 PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *total_ms, int64_t *launches) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
-    const size_t nev = (size_t)n * h->classes.size();
+    size_t per = 0, pers = 0;
+    for (const Class &c : h->classes) (c.persistent ? pers : per) += 1;
+    const size_t nev = pers + (size_t)n * per;
     std::vector<hipEvent_t> ev(2 * nev + 2, nullptr);
     for (auto &x : ev) PT_HIP(hipEventCreate(&x));
     int rc = PT_OK;
     PT_HIP(hipEventRecord(ev[2 * nev], h->stream));
     size_t k = 0;
-    for (int64_t i = 0; i < n && rc == PT_OK; ++i) {
+    if (n > 0) rc = enqueue_persistent(h, n, &ev, &k);
+    for (int64_t i = 0; i < n && rc == PT_OK && per > 0; ++i) {
         for (const Class &c : h->classes) {
+            if (c.persistent) continue;
             PT_HIP(hipEventRecord(ev[2 * k], h->stream));
             hipError_t e = pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, h->stream);
             if (e != hipSuccess) { rc = fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e)); break; }
@@ -482,12 +543,20 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
             ++k;
         }
         for (const Class &c : h->classes) {
+            if (c.persistent || rc != PT_OK) continue;
             hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, h->stream);
-            if (e != hipSuccess) { rc = fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e)); break; }
+            if (e != hipSuccess) rc = fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
         }
         if (rc == PT_OK) {
             hipError_t e = pt::launch_advance(h->T, 0, h->stream);
             if (e != hipSuccess) rc = fail(PT_EHIP, "advance launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    if (rc == PT_OK && n > 0) {
+        advance_host(h, n);
+        if (per == 0) {
+            hipError_t e = pt::launch_set_te(h->T, h->t_host, h->e_host, h->stream);
+            if (e != hipSuccess) rc = fail(PT_EHIP, "counter update failed: %s", hipGetErrorString(e));
         }
     }
     PT_HIP(hipEventRecord(ev[2 * nev + 1], h->stream));
@@ -504,10 +573,18 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
         if (sweep_ms) *sweep_ms = acc;
         if (total_ms) *total_ms = tot;
         if (launches) *launches = (int64_t)k;
-        advance_host(h, n);
     }
     for (auto &x : ev) (void)hipEventDestroy(x);
     return rc;
+}
+
+// Reports a persistent run whose blocks stopped waiting for each other.
+int check_err(pt_handle *h) {
+    int32_t err = 0;
+    PT_HIP(hipMemcpyAsync(&err, h->ws + h->L.o_err, 4, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    if (err != 0) return fail(PT_EHIP, "a persistent run timed out waiting for an exchange partner");
+    return PT_OK;
 }
 
 PT_API int pt_energy(pt_handle *h, double *h_e) {
@@ -518,7 +595,7 @@ PT_API int pt_energy(pt_handle *h, double *h_e) {
     }
     PT_HIP(hipMemcpyAsync(h_e, h->d_tmp, 8 * (size_t)h->L.total, hipMemcpyDeviceToHost, h->stream));
     PT_HIP(hipStreamSynchronize(h->stream));
-    return PT_OK;
+    return check_err(h);
 }
 
 PT_API int pt_observables(pt_handle *h, double *acc, int64_t *counts, int32_t *perm, int64_t *te) {
@@ -529,7 +606,7 @@ PT_API int pt_observables(pt_handle *h, double *acc, int64_t *counts, int32_t *p
     if (perm) PT_HIP(hipMemcpyAsync(perm, h->ws + h->L.o_perm, 4 * S, hipMemcpyDeviceToHost, h->stream));
     if (te) PT_HIP(hipMemcpyAsync(te, h->ws + h->L.o_te, 16, hipMemcpyDeviceToHost, h->stream));
     PT_HIP(hipStreamSynchronize(h->stream));
-    return PT_OK;
+    return check_err(h);
 }
 
 PT_API int pt_reset_observables(pt_handle *h) {
@@ -594,11 +671,16 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *alog, int64_t *arows, uint8_t *el
     return PT_OK;
 }
 
-PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr) {
+PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr, int32_t *persistent) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
     for (int c = 0; c < h->L.n_chains; ++c) {
         if (bpl) bpl[c] = h->L.bpl[c];
         if (wpr) wpr[c] = h->L.wpr[c];
+        if (persistent) {
+            persistent[c] = 0;
+            for (const Class &cl : h->classes)
+                if (cl.bpl == h->L.bpl[c] && cl.wpr == h->L.wpr[c]) persistent[c] = cl.persistent ? 1 : 0;
+        }
     }
     return PT_OK;
 }

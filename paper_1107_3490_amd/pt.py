@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libpt.so")
 
 PT_OK, PT_EINVAL, PT_EDOMAIN, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PT_FP64, PT_MIXED = 0, 1
+PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT = 0, 1, 2
 
 # Diagnostic ops of pt_selftest.
 OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32 = range(9)
@@ -50,7 +51,8 @@ class PtConfig(C.Structure):
                 ("coords", C.POINTER(C.c_double)), ("stream_chain", C.POINTER(C.c_uint32)),
                 ("stream_slot0", C.POINTER(C.c_uint32)), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("exchange_every", C.c_int32),
-                ("series_capacity", C.c_int64), ("log_capacity", C.c_int64)]
+                ("series_capacity", C.c_int64), ("log_capacity", C.c_int64),
+                ("schedule", C.c_int32)]
 
 
 _lib = None
@@ -77,7 +79,7 @@ def lib():
         L.pt_get_series.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
         L.pt_get_logs.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_int64), P(C.c_uint8), P(C.c_int64)]
         L.pt_time_sweeps.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double), P(C.c_int64)]
-        L.pt_get_mapping.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
+        L.pt_get_mapping.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
         L.pt_selftest.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), C.c_int64]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_destroy.restype = None
@@ -173,8 +175,10 @@ def pt_time_sweeps(h: int, n: int):
 def pt_get_mapping(h: int, n_chains: int):
     bpl = np.zeros(n_chains, dtype=np.int32)
     wpr = np.zeros(n_chains, dtype=np.int32)
-    _check(lib().pt_get_mapping(C.c_void_p(h), _ptr(bpl, C.c_int32), _ptr(wpr, C.c_int32)))
-    return bpl, wpr
+    per = np.zeros(n_chains, dtype=np.int32)
+    _check(lib().pt_get_mapping(C.c_void_p(h), _ptr(bpl, C.c_int32), _ptr(wpr, C.c_int32),
+                                _ptr(per, C.c_int32)))
+    return bpl, wpr, per
 
 
 def pt_selftest(model: dict, op: int, x, y=None) -> np.ndarray:
@@ -199,7 +203,7 @@ class Simulation:
     """A workload on the GPU: workspace, handle and typed read-backs."""
 
     def __init__(self, w, precision: Optional[str] = None, series_capacity: int = 0,
-                 log_capacity: int = 0, device: str = "cuda"):
+                 log_capacity: int = 0, device: str = "cuda", schedule: int = PT_SCHED_AUTO):
         import torch
 
         self.w = w
@@ -221,7 +225,7 @@ class Simulation:
             stream_slot0=_ptr(self._ss, C.c_uint32) if self._ss is not None else None,
             seed=int(w.seed), precision=PT_MIXED if prec == "mixed" else PT_FP64,
             exchange_every=int(w.exchange_every), series_capacity=int(series_capacity),
-            log_capacity=int(log_capacity))
+            log_capacity=int(log_capacity), schedule=int(schedule))
         nbytes = pt_workspace_bytes(self.model, self.cfg)
         if nbytes == 0:
             _check(PT_EINVAL)
@@ -291,5 +295,6 @@ class Simulation:
     def time_sweeps(self, n: int):
         return pt_time_sweeps(self.h, n)
 
-    def mapping(self) -> np.ndarray:
+    def mapping(self):
+        """(beads per lane, wavefronts per replica, persistent flag) per chain."""
         return pt_get_mapping(self.h, len(self.w.n_beads))

@@ -34,16 +34,26 @@ def _pt():
     return pt
 
 
-def run_both(w, sweeps, precision, label):
+def run_gpu(w, sweeps, precision, schedule=0, chunks=None):
+    """Runs the library; returns every observable state.  chunks splits the
+    sweeps over several pt_sweep calls."""
     pt = _pt()
-    print(f"\n[case] {label}: chains={len(w.n_beads)} N={sorted(set(w.n_beads))} "
-          f"slots={w.total_slots} sweeps={sweeps} precision={precision}", flush=True)
-    sim = pt.Simulation(w, precision=precision, series_capacity=sweeps, log_capacity=sweeps)
-    sim.sweep(sweeps)
+    sim = pt.Simulation(w, precision=precision, series_capacity=sweeps, log_capacity=sweeps,
+                        schedule=schedule)
+    for n in (chunks or [sweeps]):
+        sim.sweep(n)
     g = dict(coords=sim.coords(), energy=sim.energy(), obs=sim.observables(), series=sim.series())
     g["alog"], g["elog"] = sim.logs()
     g["e_run"], g["b_run"] = sim.running()
+    g["persistent"] = sim.mapping()[2]
     sim.close()
+    return g
+
+
+def run_both(w, sweeps, precision, label, schedule=0):
+    print(f"\n[case] {label}: chains={len(w.n_beads)} N={sorted(set(w.n_beads))} "
+          f"slots={w.total_slots} sweeps={sweeps} precision={precision} schedule={schedule}", flush=True)
+    g = run_gpu(w, sweeps, precision, schedule)
     orc = O.Simulation(w)
     r = orc.run(sweeps, accept_log=True, exch_log=True, series=True)
     o = dict(coords=orc.coords, energy=orc.energy, perm=orc.perm, alog=r["accept_log"],
@@ -164,11 +174,13 @@ def test_c1_full_run(precision):
     assert_parity(g, o, precision)
 
 
+@pytest.mark.parametrize("schedule", [1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_c2_reduced(precision):
+def test_c2_reduced(precision, schedule):
     w = I.named("c2")
-    g, o = run_both(w, 300, precision, "c2 300 sweeps")
+    g, o = run_both(w, 300, precision, "c2 300 sweeps", schedule)
     assert_parity(g, o, precision)
+    assert np.all(g["persistent"] == (1 if schedule == 2 else 0))
 
 
 def test_c3_reduced_mixed():
@@ -206,7 +218,7 @@ def test_mapping_classes():
     pt = _pt()
     w = I.make_workload([13, 100, 300, 500, 600, 2000], [2] * 6, [(0.3, 1.0)] * 6, "walk", 5, 0, "mixed")
     sim = pt.Simulation(w)
-    bpl, wpr = sim.mapping()
+    bpl, wpr, _ = sim.mapping()
     sim.close()
     assert list(bpl) == [1, 2, 8, 8, 8, 8] and list(wpr) == [1, 1, 1, 1, 2, 4]
 
@@ -239,3 +251,42 @@ def test_segment_split_and_explicit_exchange_are_deterministic():
     orc.exchange()
     assert np.array_equal(a.observables()["perm"], orc.perm)
     assert a.observables()["e"] == orc.e
+    # and the run goes on from there alike
+    a.sweep(10)
+    orc.run(10)
+    assert np.array_equal(a.observables()["perm"], orc.perm)
+    assert np.array_equal(a.coords(), orc.coords)
+
+
+def _assert_same_state(a, b):
+    for key in ("coords", "energy", "series", "alog", "elog", "e_run", "b_run"):
+        assert np.array_equal(a[key], b[key]), key
+    for key in ("perm", "counts", "acc"):
+        assert np.array_equal(a["obs"][key], b["obs"][key]), key
+    assert a["obs"]["t"] == b["obs"]["t"] and a["obs"]["e"] == b["obs"]["e"]
+
+
+@pytest.mark.parametrize("case", ["c1", "c4", "uneven_every3", "n2048", "n700_odd"])
+def test_persistent_schedule_equals_per_sweep(case):
+    """The persistent kernel (one launch, pairwise exchange synchronisation)
+    leaves every output bit-identical to one sweep launch plus one exchange
+    launch per sweep, also when the run is split over several calls."""
+    if case == "c1":
+        w, sweeps, prec, chunks = I.named("c1"), 400, "mixed", [1, 150, 249]
+    elif case == "c4":
+        w, sweeps, prec, chunks = I.named("c4"), 6, "mixed", [2, 4]
+    elif case == "uneven_every3":
+        w = I.make_workload([50, 30, 9], [7, 4, 1], [(0.2, 1.5), (0.3, 1.0), (0.5, 0.5)], "walk", 93, 0,
+                            "fp64", exchange_every=3)
+        sweeps, prec, chunks = 40, "fp64", [5, 35]
+    elif case == "n2048":
+        w = I.make_workload([2048], [6], [(0.2, 2.0)], "walk", 17, 0, "mixed")
+        sweeps, prec, chunks = 3, "mixed", [1, 2]
+    else:
+        w = I.make_workload([700], [9], [(0.2, 2.0)], "walk", 18, 0, "fp64")
+        sweeps, prec, chunks = 4, "fp64", [4]
+    print(f"\n[case] schedules {case}: slots={w.total_slots} sweeps={sweeps} {prec}", flush=True)
+    a = run_gpu(w, sweeps, prec, schedule=1)
+    b = run_gpu(w, sweeps, prec, schedule=2, chunks=chunks)
+    assert np.all(a["persistent"] == 0) and np.all(b["persistent"] == 1)
+    _assert_same_state(a, b)

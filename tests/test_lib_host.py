@@ -41,7 +41,8 @@ def _cfg(w, precision=pt.PT_FP64):
     cfg = pt.PtConfig(n_chains=len(w.n_beads), n_beads=pt._ptr(keep["n_beads"], C.c_int32),
                       n_slots=pt._ptr(keep["n_slots"], C.c_int32), beta=pt._ptr(keep["beta"], C.c_double),
                       coords=pt._ptr(keep["coords"], C.c_double), stream_chain=None, stream_slot0=None,
-                      seed=1, precision=precision, exchange_every=1, series_capacity=0, log_capacity=0)
+                      seed=1, precision=precision, exchange_every=1, series_capacity=0, log_capacity=0,
+                      schedule=0)
     return cfg, keep
 
 
