@@ -106,6 +106,10 @@ typedef struct pt_config {
                                        on the device; 0 = none                         */
     int32_t schedule;               /* PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or
                                        PT_SCHED_PERSISTENT (same results)              */
+    const int32_t *mapping;         /* [n_chains] 16*B + W (beads per lane B in
+                                       {1,2,4,8}, wavefronts per replica W in {1,2,4},
+                                       64*W*B >= N) or 0 for the default; NULL = all
+                                       default.  Results do not depend on it.          */
 } pt_config;
 
 /* How pt_sweep runs a class of chains (chains with the same mapping).
@@ -177,6 +181,42 @@ PT_API int pt_get_series(pt_handle *h, double *h_series, int64_t *rows);
 PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_rows,
                        uint8_t *h_exch_log, int64_t *exch_rows);
 
+/* Autotuner of the mapping.  For every distinct chain length of the batch it
+ * times each mapping with 64 W B in [N, max(64, 4N)) on the batch's chains of
+ * that length (their own slots, ladders, coordinates, precision and
+ * schedule) over trial_sweeps sweeps after a warm-up, in a device workspace of
+ * its own on hip_stream, and writes the fastest as 16 B + W to
+ * mapping_out[n_chains] (ready for config.mapping).  The caller's state is not
+ * touched; results of a run do not depend on the mapping.  Synchronous.
+ * Errors: as pt_init, and PT_ENOMEM when the device has no room. */
+PT_API int pt_autotune(const pt_model *model, const pt_config *config, int32_t trial_sweeps,
+                       void *hip_stream, int32_t *mapping_out);
+
+/* Decision digests, [slots][2], synchronous: per slot, [0] folds every
+ * accept word of the slot's sweeps (the words of pt_get_logs, in order) as
+ * d = mix(d ^ word), [1] folds the outcome of every exchange attempt in
+ * which the slot was the lower one as d = mix(d ^ (e << 1 | accepted)); mix
+ * is the SplitMix64 finaliser (Steele, Lea, Flood 2014), d starts at 0.
+ * Two runs with equal digests took the same decisions (Eqs. 5, 6) without
+ * keeping the logs. */
+PT_API int pt_get_digests(pt_handle *h, uint64_t *h_digests);
+
+/* Checkpoint and resume.  pt_state_bytes gives the size of the host buffer
+ * (0 and an error message for a NULL handle).  pt_get_state (synchronous)
+ * writes the run counters, the slot permutation, every conformation (AoS, as
+ * pt_get_coords), the running energies and bounds, the accumulators, the
+ * counters and the digests; it does not hold the series or logs.
+ * pt_set_state (synchronous) loads such a state into a handle made for the
+ * same chains, slots and seed (the precision, schedule and capacities may
+ * differ): the run then continues exactly as the saved run would have.
+ * Errors: PT_ENOMEM (buffer too small), PT_EINVAL (not a state, another
+ * batch, a permutation that mixes chains), PT_EDOMAIN (a broken bond),
+ * PT_EHIP.  pt_set_state also clears the failed state (PT_ESTATE) left by a
+ * persistent run that timed out. */
+PT_API size_t pt_state_bytes(pt_handle *h);
+PT_API int pt_get_state(pt_handle *h, void *h_buf, size_t bytes);
+PT_API int pt_set_state(pt_handle *h, const void *h_buf, size_t bytes);
+
 /* Timing of the sweep kernels: runs n sweeps like pt_sweep, with HIP events
  * recorded on the handle's stream around every sweep-kernel launch (a
  * persistent launch covers all n sweeps and their exchange steps), then
@@ -185,10 +225,10 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
 PT_API int pt_time_sweeps(pt_handle *h, int64_t n_sweeps, double *sweep_ms, double *total_ms,
                           int64_t *launches);
 
-/* Mapping chosen for each chain (any pointer may be NULL): beads per lane
- * (a power of two <= 8), wavefronts per replica (1, 2 or 4), the smallest
- * pair with 64 * wpr * bpl >= N, and 1 where the chain's class runs the
- * persistent schedule, else 0.  [n_chains] each. */
+/* Mapping of each chain (any pointer may be NULL): beads per lane (a power
+ * of two <= 8) and wavefronts per replica (1, 2 or 4) -- config.mapping, or
+ * by default the smallest pair with 64 * wpr * bpl >= N -- and 1 where the
+ * chain's class runs the persistent schedule, else 0.  [n_chains] each. */
 PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_per_replica,
                           int32_t *persistent);
 

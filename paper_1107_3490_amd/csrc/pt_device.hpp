@@ -37,6 +37,14 @@ __device__ __forceinline__ U4 philox10(U4 c, uint64_t seed) {
     return c;
 }
 
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA'14): the mixing step of
+// the running 64-bit digests of decisions.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 // (w + 1/2) 2^-32: a uniform deviate in (0, 1), exact in FP64.
 __device__ __forceinline__ double unit_open(uint32_t w) {
     return ((double)w + 0.5) * 0x1p-32;
@@ -115,9 +123,15 @@ __device__ __forceinline__ double fene64(const Consts &k, double r2) {
 // c_erc u (4 eps) b, c_erc = 3 |E_LJ(rc)| / (4 eps b_rc).  A pair whose FP32
 // r^2 lands on the other side of the cutoff than the FP64 one is within 6u
 // rc^2 of it, where |E_mod| <= |dE/dr^2|(rc) 6u rc^2 = c_win u (4 eps) b_rc.
-// The host sets kbound = kappa u (4 eps)(1 + 2^-8), kappa >= 62 + c_erc +
-// c_win with a margin (at least 128), and the kernels accumulate b over both
-// evaluations of every pair, inside or outside the cutoff.
+// The kernels sum the FP32 pair terms t of a move in FP32 (in-lane tree,
+// butterfly and the tree over wavefronts: a pairwise tree of depth <= 11),
+// which adds at most 11.01u sum |t|; since |E_LJ(rc)| <= (4 eps) b for any
+// pair inside the cutoff, |t| <= 2 (4 eps)(b_new + b_old)(1 + 2^-20), so the
+// sum adds at most 22.1u (4 eps) per unit of b.  The host sets kbound =
+// kappa u (4 eps)(1 + 2^-8), kappa >= 62 + c_erc + c_win with a margin (at
+// least 128), plus 24 for the sum, and the kernels accumulate b over both
+// evaluations of every pair, inside or outside the cutoff; the FP32 sum of
+// the b (depth <= 11, at most 11.01u low) is scaled by 1 + 2^-20 before use.
 struct Lj32 {
     float e;  // term
     float b;  // s6^2 + s6

@@ -48,6 +48,7 @@ struct Tables {
     int64_t *done;               // persistent runs: sweeps completed by conformation q
     int64_t *dec;                // persistent runs: exchange steps decided for q's pair
     int32_t *err;                // persistent runs: nonzero after a synchronisation timeout
+    uint64_t *dig;               // [S][2] digests of the accept words and exchange outcomes
     // per chain c
     const int32_t *chain_n;      // beads
     const int32_t *chain_slots;  // slots

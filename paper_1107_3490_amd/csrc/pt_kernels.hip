@@ -46,18 +46,19 @@ struct Leaf64 {
 };
 
 struct LeafMx {
-    double t;
-    float b;
+    float t, b;
     __device__ LeafMx operator+(const LeafMx &o) const { return LeafMx{t + o.t, b + o.b}; }
 };
 
 __device__ __forceinline__ double dabs(double v) { return __builtin_fabs(v); }
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // Bound on |E_run - exact sum of the FP64-order terms| added by one accepted
 // move scored in the FP64 order: the leaf differences (u each), the tree over
 // the leaves (depth log2 NP, u |partial| each), the two bond differences, their
 // sum and the final addition, all with a factor-two margin (2^-52 for u).
+// abs_leaves must be an upper bound on the sum of the leaf magnitudes.
 __device__ __forceinline__ double bound64(int log_np, double abs_leaves, double dfl, double dfr,
                                           double de) {
     return 0x1p-52 * ((double)(log_np + 2) * abs_leaves + 2.0 * (dabs(dfl) + dabs(dfr)) + dabs(de));
@@ -213,7 +214,10 @@ struct MoveRec {
     int pad;
 };
 
-// Sum of the W per-wavefront values v[0..W) as a pairwise tree.
+// Sum of the W per-wavefront values v[0..W) as a pairwise tree, in FP64
+// (tree_w) or, for values that are FP32 sums, in FP32 (tree_wf), so that the
+// whole sum is the pairwise tree over the padded bead range in one precision
+// for every mapping.
 template <int W>
 __device__ __forceinline__ double tree_w(const double *v) {
     if constexpr (W == 1) return v[0];
@@ -221,11 +225,22 @@ __device__ __forceinline__ double tree_w(const double *v) {
     else return (v[0] + v[1]) + (v[2] + v[3]);
 }
 
+template <int W>
+__device__ __forceinline__ float tree_wf(const double *v) {
+    if constexpr (W == 1) return (float)v[0];
+    else if constexpr (W == 2) return (float)v[0] + (float)v[1];
+    else return ((float)v[0] + (float)v[1]) + ((float)v[2] + (float)v[3]);
+}
+
+// ceil(log2 n), n >= 2: the depth of the pairwise tree over n leaves padded
+// with zeros to a power of two (levels over padding add exact zeros).
+__device__ __forceinline__ int log2c(int n) { return 32 - __builtin_clz((unsigned)(n - 1)); }
+
 // LDS of a sweep block: the replica mirror, the batch's move records and the
 // per-wavefront partial sums (double-buffered over consecutive moves).
 template <int B, int W>
 struct SweepLds {
-    static constexpr int MB = (W >= 4) ? 32 : 64;  // moves per batch (LDS budget at W = 4)
+    static constexpr int MB = (Geo<B, W>::NP >= 2048) ? 32 : 64;  // moves per batch (LDS budget)
     double xyz[3 * Geo<B, W>::NP];
     MoveRec rec[MB];
     double part[2][2][W];
@@ -257,6 +272,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                            ? T.accept_log + t64 * T.words_total + T.word_off[g]
                            : nullptr;
     uint64_t logword = 0;
+    uint64_t digest = (tid == 0) ? T.dig[2 * g] : 0;
 
     for (int m0 = 0; m0 < n; m0 += MB) {
         __syncthreads();  // commits of the previous batch visible, rec[] free
@@ -360,9 +376,9 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                     const bool self = mine && b == slot;
                     const float tt = self ? 0.0f : pn.e - po.e;
                     const float bb = self ? 0.0f : pn.b + po.b;
-                    return LeafMx{(double)tt, bb};
+                    return LeafMx{tt, bb};
                 });
-                double sm = wave_tree(s.t);
+                double sm = (double)wave_tree(s.t);
                 double bsum = (double)wave_tree(s.b);
                 if constexpr (W > 1) {
                     if (lane == 0) {
@@ -370,8 +386,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                         S.part[i & 1][1][wv] = bsum;
                     }
                     __syncthreads();
-                    sm = tree_w<W>(S.part[i & 1][0]);
-                    bsum = tree_w<W>(S.part[i & 1][1]);
+                    sm = (double)tree_wf<W>(S.part[i & 1][0]);
+                    bsum = (double)tree_wf<W>(S.part[i & 1][1]);
                 }
                 const double bs = K.kbound * bsum;
                 const double dem = sm + df;
@@ -408,7 +424,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 const double de = sc + df;
                 acc = (de <= 0.0) || (beta * de < th);
                 de_used = de;
-                bm = bound64(G::LOG_NP, ab, dfl, dfr, de);
+                bm = bound64(log2c(n), ab, dfl, dfr, de);
             }
             if (acc) {
                 if (mine) {
@@ -438,10 +454,13 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             wave_sync();
         }
         logword |= bits << (m0 & 63);
-        if (logrow != nullptr && tid == 0 && (((m0 + MB) & 63) == 0 || m0 + MB >= n))
-            logrow[m0 >> 6] = logword;
+        if (tid == 0 && (((m0 + MB) & 63) == 0 || m0 + MB >= n)) {
+            if (logrow != nullptr) logrow[m0 >> 6] = logword;
+            digest = mix64(digest ^ logword);
+        }
         if (((m0 + MB) & 63) == 0) logword = 0;
     }
+    if (tid == 0) T.dig[2 * g] = digest;
     __syncthreads();
 }
 
@@ -465,7 +484,7 @@ __device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S,
         bool resync = false;
         if (!(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
             E = energy_wave<B, W>(X, Y, Z, n, K);
-            Bd = bound_energy(K, G::LOG_NP, n, E, 0.0);
+            Bd = bound_energy(K, log2c(n), n, E, 0.0);
             resync = true;
         }
         if (tid == 0) {
@@ -513,8 +532,11 @@ __device__ __forceinline__ void load_regs(const SweepLds<B, W> &S, double (&rx)[
 }
 
 // One sweep of every slot in `list` (one block per slot), then its record.
+// Classes of 1024 or more lanes' worth of beads (64 W B >= 1024) are built for
+// three blocks per CU: the register cap costs a few spills outside the pair
+// loop but hides more latency than it adds (measured on N = 2000).
 template <int B, int W, bool MIXED>
-__global__ __launch_bounds__(64 * W) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
+__global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
     using G = Geo<B, W>;
     __shared__ SweepLds<B, W> S;
     const int g = list[blockIdx.x];
@@ -552,7 +574,7 @@ __global__ __launch_bounds__(64) void k_energy(const Tables T, const int32_t *__
     const double e = energy_wave<B, W>(X, Y, Z, n, T.k);
     if (threadIdx.x == 0) {
         out_e[id] = e;
-        if (out_b != nullptr) out_b[id] = bound_energy(T.k, G::LOG_NP, n, e, 0.0);
+        if (out_b != nullptr) out_b[id] = bound_energy(T.k, log2c(n), n, e, 0.0);
     }
 }
 
@@ -573,8 +595,8 @@ __device__ __forceinline__ bool exch_decide(const Tables &T, int c, int i, int64
     const U4 w = philox10(U4{(uint32_t)i, (uint32_t)e, T.chain_sid[c], 2u}, T.seed);
     const double pl = det_log(unit_open(w.x));
     const double dd = e1 - e2;
-    const double tot = (bb1 + bound_energy(T.k, G::LOG_NP, n, e1, bb1) + bb2 +
-                        bound_energy(T.k, G::LOG_NP, n, e2, bb2)) * (1.0 + 0x1p-20) +
+    const double tot = (bb1 + bound_energy(T.k, log2c(n), n, e1, bb1) + bb2 +
+                        bound_energy(T.k, log2c(n), n, e2, bb2)) * (1.0 + 0x1p-20) +
                        0x1p-50 * dabs(dd);
     const double d1 = db * (dd - tot), d2 = db * (dd + tot);
     const double dlo = (d1 < d2) ? d1 : d2, dhi = (d1 < d2) ? d2 : d1;
@@ -587,9 +609,9 @@ __device__ __forceinline__ bool exch_decide(const Tables &T, int c, int i, int64
     const double c2 = canon(1);
     const double d = db * (c1 - c2);
     e1 = c1;
-    bb1 = bound_energy(T.k, G::LOG_NP, n, c1, 0.0);
+    bb1 = bound_energy(T.k, log2c(n), n, c1, 0.0);
     e2 = c2;
-    bb2 = bound_energy(T.k, G::LOG_NP, n, c2, 0.0);
+    bb2 = bound_energy(T.k, log2c(n), n, c2, 0.0);
     return (d >= 0.0) || (pl < d);
 }
 
@@ -607,6 +629,7 @@ __device__ __forceinline__ void exch_commit(const Tables &T, int g, int64_t e, i
         T.slot_of[q2] = g;
     }
     if (T.exch_log != nullptr && e < T.log_cap) T.exch_log[e * T.total_slots + g] = acc ? 1 : 0;
+    T.dig[2 * g + 1] = mix64(T.dig[2 * g + 1] ^ (((uint64_t)e << 1) | (acc ? 1u : 0u)));
 }
 
 // One exchange step for the chains in `list`: wavefront p of a chain handles
@@ -674,7 +697,10 @@ __device__ __forceinline__ bool wait_ge(const int64_t *p, int64_t v, int32_t *er
 // publishes its running energy, coordinates and conformation id and sets
 // done[g] = t + 1; the holder of the lower slot of an attempted pair waits for
 // its partner's flag, decides exactly as k_exchange does, writes the new slot
-// assignment and sets dec[g+1] = t + 1, which the partner waits for.
+// assignment and sets dec[g+1] = t + 1, which the partner waits for.  Inside
+// the band the partner's FP64-order energy is computed from a copy of its
+// replica in the block's LDS, which is then refilled from the block's own
+// published copy.
 template <int B, int W, bool MIXED>
 __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *__restrict__ list,
                                                 int64_t n_sweeps, int64_t t0, int64_t e0) {
@@ -723,11 +749,21 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
                     double e2 = T.e_run[q2], bb2 = T.b_run[q2];
                     bool band = false;
                     const double *c2 = T.coords + T.coord_off[q2];
-                    const double *c1 = S.xyz;
+                    double *const lds = S.xyz;
                     const Consts K = T.k;
-                    auto canon = [c1, c2, n, K](int which) {
-                        const double *p = which == 0 ? c1 : c2;
-                        return energy_wave<B, W>(p, p + G::NP, p + 2 * G::NP, n, K);
+                    auto canon = [lds, c2, cq, n, K](int which) {
+                        if (which == 1) {
+                            wave_sync();
+                            copy_replica<B, W, 64>(lds, c2);
+                            wave_sync();
+                        }
+                        const double v = energy_wave<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K);
+                        if (which == 1) {
+                            wave_sync();
+                            copy_replica<B, W, 64>(lds, cq);
+                            wave_sync();
+                        }
+                        return v;
                     };
                     const bool acc = exch_decide<B, W>(T, c, i, e, n, g, e1, bb1, e2, bb2, band, canon);
                     if (tid == 0) {
@@ -891,7 +927,13 @@ hipError_t run_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64
         case 2 * 16 + 1: return CALL(2, 1);   \
         case 4 * 16 + 1: return CALL(4, 1);   \
         case 8 * 16 + 1: return CALL(8, 1);   \
+        case 1 * 16 + 2: return CALL(1, 2);   \
+        case 2 * 16 + 2: return CALL(2, 2);   \
+        case 4 * 16 + 2: return CALL(4, 2);   \
         case 8 * 16 + 2: return CALL(8, 2);   \
+        case 1 * 16 + 4: return CALL(1, 4);   \
+        case 2 * 16 + 4: return CALL(2, 4);   \
+        case 4 * 16 + 4: return CALL(4, 4);   \
         case 8 * 16 + 4: return CALL(8, 4);   \
         default: return hipErrorInvalidValue; \
     }

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <new>
 #include <string>
@@ -67,7 +68,7 @@ struct Layout {
     size_t o_slot_chain, o_slot_index, o_slot_gid, o_beta, o_perm, o_acc, o_counts, o_word_off;
     size_t o_coord_off, o_e_run, o_b_run, o_coords, o_slot_of, o_done, o_dec, o_err;
     size_t o_chain_n, o_chain_slots, o_chain_slot0, o_chain_sid;
-    size_t o_te, o_lists, o_tmp, o_alog, o_elog, o_series;
+    size_t o_te, o_lists, o_tmp, o_alog, o_elog, o_series, o_dig;
     size_t bytes = 0;
     int64_t log_cap = 0, series_cap = 0;
     int lists_len = 0;
@@ -91,6 +92,14 @@ int validate(const pt_model *m, const pt_config *c) {
     int64_t total = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
         if (c->n_beads[ch] < 2) return fail(PT_EINVAL, "chain %d: n_beads must be >= 2", ch);
+        if (c->mapping != nullptr && c->mapping[ch] != 0) {
+            const int code = c->mapping[ch], B = code >> 4, W = code & 15;
+            const bool okb = B == 1 || B == 2 || B == 4 || B == 8, okw = W == 1 || W == 2 || W == 4;
+            if (!okb || !okw || (code & ~0xFF) != 0)
+                return fail(PT_EINVAL, "chain %d: mapping %d is not 16*B + W with B in {1,2,4,8}, W in {1,2,4}", ch, code);
+            if (64 * W * B < c->n_beads[ch])
+                return fail(PT_EINVAL, "chain %d: mapping B=%d W=%d holds %d < %d beads", ch, B, W, 64 * W * B, c->n_beads[ch]);
+        }
         if (c->n_beads[ch] > kMaxBeads) return fail(PT_EUNSUPPORTED, "chain %d: %d beads exceeds %d", ch, c->n_beads[ch], kMaxBeads);
         if (c->n_slots[ch] < 1) return fail(PT_EINVAL, "chain %d: n_slots must be >= 1", ch);
         total += c->n_slots[ch];
@@ -127,7 +136,8 @@ pt::Consts make_consts(const pt_model *m, bool mixed) {
     const double c_erc = 3.0 * fabs(k.e_rc) / (k.four_eps * brc);
     const double slope = (3.0 * k.four_eps / k.rc2) * fabs(2.0 * s6c * s6c - s6c);  // |dE/dr^2| at rc
     const double c_win = slope * 6.0 * k.rc2 * (1.0 + 0x1p-4) / (k.four_eps * brc);
-    const double kappa = std::max(128.0, ceil(1.25 * (62.0 + c_erc + c_win)));
+    // + 24: the FP32 pair sums (pairwise trees of depth <= 11).
+    const double kappa = std::max(128.0, ceil(1.25 * (62.0 + c_erc + c_win))) + 24.0;
     k.kbound = kappa * 0x1p-24 * k.four_eps * (1.0 + 0x1p-8);
     k.neg_floor = (m->epsilon + fabs(k.e_rc)) * (1.0 + 0x1p-30);
     k.resync_rel = mixed ? 0x1p-10 : 0x1p-40;
@@ -146,7 +156,12 @@ Layout plan(const pt_config *c) {
     L.word_off.resize(total);
     int g = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
-        mapping(c->n_beads[ch], &L.bpl[ch], &L.wpr[ch]);
+        if (c->mapping != nullptr && c->mapping[ch] != 0) {
+            L.bpl[ch] = c->mapping[ch] >> 4;
+            L.wpr[ch] = c->mapping[ch] & 15;
+        } else {
+            mapping(c->n_beads[ch], &L.bpl[ch], &L.wpr[ch]);
+        }
         for (int s = 0; s < c->n_slots[ch]; ++s, ++g) {
             L.coord_off[g] = L.coord_total;
             L.word_off[g] = L.words_total;
@@ -182,6 +197,7 @@ Layout plan(const pt_config *c) {
     L.o_chain_slot0 = take(4 * C);
     L.o_chain_sid = take(4 * C);
     L.o_te = take(16);
+    L.o_dig = take(16 * S);
     L.o_lists = take(4 * (size_t)L.lists_len);
     L.o_tmp = take(8 * S);
     L.o_alog = take(8 * (size_t)L.words_total * (size_t)L.log_cap);
@@ -225,6 +241,8 @@ struct pt_handle {
     int64_t t_host = 0, e_host = 0;  // counters as enqueued
     hipGraphExec_t graph1 = nullptr, graph16 = nullptr;
     double *d_tmp = nullptr;
+    uint64_t seed = 0;
+    bool failed = false;  // a persistent run timed out; only pt_set_state recovers
 };
 
 namespace {
@@ -336,6 +354,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     h->ws = (char *)d_workspace;
     h->mixed = cfg->precision == PT_MIXED;
     h->exchange_every = cfg->exchange_every;
+    h->seed = cfg->seed;
     h->n_beads.assign(cfg->n_beads, cfg->n_beads + C);
     h->n_slots.assign(cfg->n_slots, cfg->n_slots + C);
     char *w = h->ws;
@@ -361,6 +380,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.done = (int64_t *)(w + L.o_done);
     T.dec = (int64_t *)(w + L.o_dec);
     T.err = (int32_t *)(w + L.o_err);
+    T.dig = (uint64_t *)(w + L.o_dig);
     T.accept_log = L.log_cap > 0 ? (uint64_t *)(w + L.o_alog) : nullptr;
     T.log_cap = L.log_cap;
     T.words_total = L.words_total;
@@ -427,6 +447,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_done, 0, 8 * (size_t)S, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_dec, 0, 8 * (size_t)S, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_err, 0, 16, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_dig, 0, 16 * (size_t)S, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_counts, 0, 8 * pt::PT_NCOUNTS * (size_t)S, h->stream);
     if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_elog, 0xFF, (size_t)S * L.log_cap, h->stream);
     if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_alog, 0, 8 * (size_t)L.words_total * L.log_cap, h->stream);
@@ -478,6 +499,7 @@ bool any_per_sweep(const pt_handle *h) {
 
 PT_API int pt_sweep(pt_handle *h, int64_t n) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    if (h->failed) return fail(PT_ESTATE, "the handle failed earlier; restore a state with pt_set_state");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
     if (n == 0) return PT_OK;
     int rc = enqueue_persistent(h, n, nullptr, nullptr);
@@ -511,6 +533,7 @@ PT_API int pt_sweep(pt_handle *h, int64_t n) {
 
 PT_API int pt_exchange(pt_handle *h) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    if (h->failed) return fail(PT_ESTATE, "the handle failed earlier; restore a state with pt_set_state");
     for (const Class &c : h->classes) {
         hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 1, h->stream);
         if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
@@ -523,6 +546,7 @@ PT_API int pt_exchange(pt_handle *h) {
 
 PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *total_ms, int64_t *launches) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
+    if (h->failed) return fail(PT_ESTATE, "the handle failed earlier; restore a state with pt_set_state");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
     size_t per = 0, pers = 0;
     for (const Class &c : h->classes) (c.persistent ? pers : per) += 1;
@@ -583,7 +607,10 @@ int check_err(pt_handle *h) {
     int32_t err = 0;
     PT_HIP(hipMemcpyAsync(&err, h->ws + h->L.o_err, 4, hipMemcpyDeviceToHost, h->stream));
     PT_HIP(hipStreamSynchronize(h->stream));
-    if (err != 0) return fail(PT_EHIP, "a persistent run timed out waiting for an exchange partner");
+    if (err != 0) {
+        h->failed = true;
+        return fail(PT_EHIP, "a persistent run timed out waiting for an exchange partner");
+    }
     return PT_OK;
 }
 
@@ -723,3 +750,234 @@ PT_API void pt_destroy(pt_handle *h) {
 }
 
 PT_API const char *pt_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------ state I/O --
+namespace {
+
+constexpr uint64_t kStateMagic = 0x3145544154535450ull;  // "PTSTATE1"
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t n_chains, precision;
+    int64_t total, coord_doubles, t, e;
+    uint64_t seed;
+};
+
+size_t state_bytes(const pt_handle *h) {
+    const size_t C = (size_t)h->L.n_chains, S = (size_t)h->L.total;
+    size_t cd = 0;
+    for (size_t c = 0; c < C; ++c) cd += 3 * (size_t)h->n_beads[c] * (size_t)h->n_slots[c];
+    return sizeof(StateHeader) + 8 * C + 8 * ((4 * S + 7) / 8) + 8 * cd + 8 * S * (2 + 5 + pt::PT_NCOUNTS + 2);
+}
+
+}  // namespace
+
+PT_API size_t pt_state_bytes(pt_handle *h) {
+    if (h == nullptr) {
+        fail(PT_EINVAL, "NULL handle");
+        return 0;
+    }
+    return state_bytes(h);
+}
+
+PT_API int pt_get_digests(pt_handle *h, uint64_t *h_dig) {
+    if (h == nullptr || h_dig == nullptr) return fail(PT_EINVAL, "NULL argument");
+    PT_HIP(hipMemcpyAsync(h_dig, h->ws + h->L.o_dig, 16 * (size_t)h->L.total, hipMemcpyDeviceToHost, h->stream));
+    PT_HIP(hipStreamSynchronize(h->stream));
+    return PT_OK;
+}
+
+PT_API int pt_get_state(pt_handle *h, void *buf, size_t bytes) {
+    if (h == nullptr || buf == nullptr) return fail(PT_EINVAL, "NULL argument");
+    const size_t need = state_bytes(h);
+    if (bytes < need) return fail(PT_ENOMEM, "state buffer of %zu bytes is smaller than the %zu needed", bytes, need);
+    const int C = h->L.n_chains, S = h->L.total;
+    char *p = (char *)buf;
+    std::memset(p, 0, need);
+    StateHeader hd{};
+    hd.magic = kStateMagic;
+    hd.n_chains = C;
+    hd.precision = h->mixed ? PT_MIXED : PT_FP64;
+    hd.total = S;
+    hd.t = h->t_host;
+    hd.e = h->e_host;
+    hd.seed = h->seed;
+    size_t cd = 0;
+    for (int c = 0; c < C; ++c) cd += 3 * (size_t)h->n_beads[c] * (size_t)h->n_slots[c];
+    hd.coord_doubles = (int64_t)cd;
+    std::memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    std::memcpy(p, h->n_beads.data(), 4 * (size_t)C);
+    std::memcpy(p + 4 * (size_t)C, h->n_slots.data(), 4 * (size_t)C);
+    p += 8 * (size_t)C;
+    int32_t *perm = (int32_t *)p;
+    p += 8 * ((4 * (size_t)S + 7) / 8);
+    double *coords = (double *)p;
+    p += 8 * cd;
+    double *e_run = (double *)p, *b_run = e_run + S, *acc = b_run + S;
+    int64_t *counts = (int64_t *)(acc + 5 * (size_t)S);
+    uint64_t *dig = (uint64_t *)(counts + pt::PT_NCOUNTS * (size_t)S);
+    int rc = pt_observables(h, acc, counts, perm, nullptr);
+    if (rc == PT_OK) rc = pt_get_running(h, e_run, b_run);
+    if (rc == PT_OK) rc = pt_get_coords(h, coords);
+    if (rc == PT_OK) rc = pt_get_digests(h, dig);
+    return rc;
+}
+
+PT_API int pt_set_state(pt_handle *h, const void *buf, size_t bytes) {
+    if (h == nullptr || buf == nullptr) return fail(PT_EINVAL, "NULL argument");
+    const size_t need = state_bytes(h);
+    if (bytes < need) return fail(PT_EINVAL, "state of %zu bytes is shorter than the %zu this handle needs", bytes, need);
+    const int C = h->L.n_chains, S = h->L.total;
+    const char *p = (const char *)buf;
+    StateHeader hd;
+    std::memcpy(&hd, p, sizeof hd);
+    if (hd.magic != kStateMagic) return fail(PT_EINVAL, "not a saved state");
+    if (hd.n_chains != C || hd.total != S || hd.seed != h->seed)
+        return fail(PT_EINVAL, "the state belongs to another batch (chains, slots or seed differ)");
+    if (hd.t < 0 || hd.e < 0) return fail(PT_EINVAL, "negative run counters in the state");
+    p += sizeof hd;
+    const int32_t *nb = (const int32_t *)p, *ns = nb + C;
+    for (int c = 0; c < C; ++c)
+        if (nb[c] != h->n_beads[c] || ns[c] != h->n_slots[c])
+            return fail(PT_EINVAL, "chain %d: beads or slots differ from this handle's", c);
+    p += 8 * (size_t)C;
+    const int32_t *perm = (const int32_t *)p;
+    p += 8 * ((4 * (size_t)S + 7) / 8);
+    const double *coords = (const double *)p;
+    p += 8 * (size_t)hd.coord_doubles;
+    const double *e_run = (const double *)p, *b_run = e_run + S, *acc = b_run + S;
+    const int64_t *counts = (const int64_t *)(acc + 5 * (size_t)S);
+    const uint64_t *dig = (const uint64_t *)(counts + pt::PT_NCOUNTS * (size_t)S);
+    // Permutation within each chain's slots; coordinates finite with intact bonds.
+    std::vector<int32_t> slot_of(S, -1);
+    std::vector<double> swz((size_t)h->L.coord_total);
+    {
+        int g = 0;
+        int64_t src = 0;
+        for (int c = 0; c < C; ++c) {
+            const int n = h->n_beads[c], B = h->L.bpl[c], W = h->L.wpr[c], NP = 64 * W * B;
+            const int g0 = g;
+            for (int s = 0; s < h->n_slots[c]; ++s, ++g) {
+                const int q = perm[g];
+                if (q < g0 || q >= g0 + h->n_slots[c] || slot_of[q] >= 0)
+                    return fail(PT_EINVAL, "slot %d: the permutation is not one of chain %d's slots", g, c);
+                slot_of[q] = g;
+                const double *xyz = coords + src;  // conformation g (started in slot g)
+                for (int j = 0; j < 3 * n; ++j)
+                    if (!isfinite(xyz[j])) return fail(PT_EINVAL, "conformation %d: non-finite coordinate", g);
+                for (int j = 0; j + 1 < n; ++j)
+                    if (!(fene_y(h->k, xyz + 3 * j, xyz + 3 * (j + 1)) > 0.0))
+                        return fail(PT_EDOMAIN, "conformation %d: bond (%d,%d) at or beyond r0 +- R", g, j, j + 1);
+                double *dst = swz.data() + h->L.coord_off[g];
+                for (int j = 0; j < NP; ++j) {
+                    const int pp = swizzle(j, B, W);
+                    dst[pp] = (j < n) ? xyz[3 * j] : kSentinel;
+                    dst[NP + pp] = (j < n) ? xyz[3 * j + 1] : 0.0;
+                    dst[2 * NP + pp] = (j < n) ? xyz[3 * j + 2] : 0.0;
+                }
+                src += 3 * (int64_t)n;
+            }
+        }
+    }
+    char *w = h->ws;
+    const int64_t te[2] = {hd.t, hd.e};
+    auto up = [&](size_t off, const void *src, size_t n) {
+        return hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, h->stream);
+    };
+    hipError_t e = up(h->L.o_coords, swz.data(), 8 * swz.size());
+    if (e == hipSuccess) e = up(h->L.o_perm, perm, 4 * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_slot_of, slot_of.data(), 4 * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_e_run, e_run, 8 * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_b_run, b_run, 8 * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_acc, acc, 8 * 5 * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_counts, counts, 8 * pt::PT_NCOUNTS * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_dig, dig, 16 * (size_t)S);
+    if (e == hipSuccess) e = up(h->L.o_te, te, 16);
+    // Pair flags of the persistent schedule are keyed by sweep index: clear them.
+    if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_done, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_dec, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_err, 0, 16, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(PT_EHIP, "state upload failed: %s", hipGetErrorString(e));
+    h->t_host = hd.t;
+    h->e_host = hd.e;
+    h->failed = false;
+    return PT_OK;
+}
+
+// -------------------------------------------------------------- autotune --
+PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t trial_sweeps, void *hip_stream,
+                       int32_t *out) {
+    int rc = validate(model, cfg);
+    if (rc != PT_OK) return rc;
+    if (out == nullptr || trial_sweeps < 1) return fail(PT_EINVAL, "mapping_out must be non-NULL and trial_sweeps >= 1");
+    const int C = cfg->n_chains;
+    // Offsets of each chain's slots and coordinates in the caller's arrays.
+    std::vector<int64_t> slot0(C + 1, 0), coord0(C + 1, 0);
+    for (int c = 0; c < C; ++c) {
+        slot0[c + 1] = slot0[c] + cfg->n_slots[c];
+        coord0[c + 1] = coord0[c] + 3 * (int64_t)cfg->n_beads[c] * cfg->n_slots[c];
+    }
+    std::map<int, std::vector<int>> by_n;
+    for (int c = 0; c < C; ++c) by_n[cfg->n_beads[c]].push_back(c);
+    for (auto &kv : by_n) {
+        const int n = kv.first;
+        const std::vector<int> &chains = kv.second;
+        std::vector<int> cand;
+        for (int W : {1, 2, 4})
+            for (int B : {1, 2, 4, 8}) {
+                const int np = 64 * W * B;
+                if (np >= n && np < std::max(65, 4 * n)) cand.push_back(16 * B + W);
+            }
+        int best = 0;
+        if (cand.size() == 1) {
+            best = cand[0];
+        } else {
+            // The chains of this length as a batch of their own.
+            std::vector<int32_t> nb, ns, mp;
+            std::vector<uint32_t> sc, s0;
+            std::vector<double> beta, xyz;
+            for (int c : chains) {
+                nb.push_back(cfg->n_beads[c]);
+                ns.push_back(cfg->n_slots[c]);
+                sc.push_back(cfg->stream_chain ? cfg->stream_chain[c] : (uint32_t)c);
+                s0.push_back(cfg->stream_slot0 ? cfg->stream_slot0[c] : (uint32_t)slot0[c]);
+                beta.insert(beta.end(), cfg->beta + slot0[c], cfg->beta + slot0[c + 1]);
+                xyz.insert(xyz.end(), cfg->coords + coord0[c], cfg->coords + coord0[c + 1]);
+            }
+            pt_config t = *cfg;
+            t.n_chains = (int32_t)chains.size();
+            t.n_beads = nb.data();
+            t.n_slots = ns.data();
+            t.beta = beta.data();
+            t.coords = xyz.data();
+            t.stream_chain = sc.data();
+            t.stream_slot0 = s0.data();
+            t.series_capacity = 0;
+            t.log_capacity = 0;
+            double best_ms = 0.0;
+            for (int code : cand) {
+                mp.assign(chains.size(), code);
+                t.mapping = mp.data();
+                const size_t bytes = plan(&t).bytes;
+                void *ws = nullptr;
+                if (hipMalloc(&ws, bytes) != hipSuccess) return fail(PT_ENOMEM, "autotune: no room for %zu bytes", bytes);
+                pt_handle *h = nullptr;
+                rc = pt_init(model, &t, ws, bytes, hip_stream, &h);
+                double ms = 0.0;
+                if (rc == PT_OK) rc = pt_sweep(h, std::min<int64_t>(trial_sweeps, 4));
+                if (rc == PT_OK) rc = pt_time_sweeps(h, trial_sweeps, nullptr, &ms, nullptr);
+                if (h) pt_destroy(h);
+                (void)hipFree(ws);
+                if (rc != PT_OK) return rc;
+                if (best == 0 || ms < best_ms) {
+                    best = code;
+                    best_ms = ms;
+                }
+            }
+        }
+        for (int c : chains) out[c] = best;
+    }
+    return PT_OK;
+}

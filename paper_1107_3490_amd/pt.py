@@ -28,10 +28,11 @@ PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT = 0, 1, 2
 # Diagnostic ops of pt_selftest.
 OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32 = range(9)
 
-EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_sweep", "pt_exchange", "pt_energy",
+EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_autotune", "pt_sweep", "pt_exchange", "pt_energy",
            "pt_observables", "pt_reset_observables", "pt_get_coords", "pt_get_running",
-           "pt_get_series", "pt_get_logs", "pt_time_sweeps", "pt_get_mapping", "pt_selftest",
-           "pt_destroy", "pt_last_error")
+           "pt_get_series", "pt_get_logs", "pt_get_digests", "pt_state_bytes", "pt_get_state",
+           "pt_set_state", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
+           "pt_last_error")
 
 
 class PtError(RuntimeError):
@@ -52,7 +53,7 @@ class PtConfig(C.Structure):
                 ("stream_slot0", C.POINTER(C.c_uint32)), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("exchange_every", C.c_int32),
                 ("series_capacity", C.c_int64), ("log_capacity", C.c_int64),
-                ("schedule", C.c_int32)]
+                ("schedule", C.c_int32), ("mapping", C.POINTER(C.c_int32))]
 
 
 _lib = None
@@ -80,13 +81,19 @@ def lib():
         L.pt_get_logs.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_int64), P(C.c_uint8), P(C.c_int64)]
         L.pt_time_sweeps.argtypes = [C.c_void_p, C.c_int64, P(C.c_double), P(C.c_double), P(C.c_int64)]
         L.pt_get_mapping.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+        L.pt_get_digests.argtypes = [C.c_void_p, P(C.c_uint64)]
+        L.pt_autotune.argtypes = [P(PtModel), P(PtConfig), C.c_int32, C.c_void_p, P(C.c_int32)]
+        L.pt_state_bytes.argtypes = [C.c_void_p]
+        L.pt_state_bytes.restype = C.c_size_t
+        L.pt_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.pt_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.pt_selftest.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), C.c_int64]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_destroy.restype = None
         L.pt_last_error.argtypes = []
         L.pt_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("pt_workspace_bytes", "pt_destroy", "pt_last_error"):
+            if name not in ("pt_workspace_bytes", "pt_state_bytes", "pt_destroy", "pt_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -181,6 +188,26 @@ def pt_get_mapping(h: int, n_chains: int):
     return bpl, wpr, per
 
 
+def pt_get_digests(h: int, n_slots: int) -> np.ndarray:
+    out = np.zeros((n_slots, 2), dtype=np.uint64)
+    _check(lib().pt_get_digests(C.c_void_p(h), _ptr(out, C.c_uint64)))
+    return out
+
+
+def pt_get_state(h: int) -> bytes:
+    n = lib().pt_state_bytes(C.c_void_p(h))
+    if n == 0:
+        _check(PT_EINVAL)
+    buf = C.create_string_buffer(n)
+    _check(lib().pt_get_state(C.c_void_p(h), buf, n))
+    return buf.raw
+
+
+def pt_set_state(h: int, state: bytes) -> None:
+    buf = C.create_string_buffer(bytes(state), len(state))
+    _check(lib().pt_set_state(C.c_void_p(h), buf, len(state)))
+
+
 def pt_selftest(model: dict, op: int, x, y=None) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
     n = x.size // 4 if op == OP_PHILOX else x.size
@@ -197,13 +224,40 @@ def pt_destroy(h: int) -> None:
     lib().pt_destroy(C.c_void_p(h))
 
 
+def autotune(w, precision: Optional[str] = None, schedule: int = PT_SCHED_AUTO,
+             trial_sweeps: int = 20) -> np.ndarray:
+    """pt_autotune on workload w: one mapping code (16 B + W) per chain."""
+    import torch
+
+    prec = precision or w.precision
+    nb = np.array(w.n_beads, dtype=np.int32)
+    ns = np.array(w.n_slots, dtype=np.int32)
+    beta = np.ascontiguousarray(w.betas, dtype=np.float64)
+    xyz = np.ascontiguousarray(w.coords, dtype=np.float64)
+    sc = np.array(w.stream_chain, dtype=np.uint32) if w.stream_chain is not None else None
+    ss = np.array(w.stream_slot0, dtype=np.uint32) if w.stream_slot0 is not None else None
+    cfg = PtConfig(n_chains=len(w.n_beads), n_beads=_ptr(nb, C.c_int32), n_slots=_ptr(ns, C.c_int32),
+                   beta=_ptr(beta, C.c_double), coords=_ptr(xyz, C.c_double),
+                   stream_chain=_ptr(sc, C.c_uint32) if sc is not None else None,
+                   stream_slot0=_ptr(ss, C.c_uint32) if ss is not None else None,
+                   seed=int(w.seed), precision=PT_MIXED if prec == "mixed" else PT_FP64,
+                   exchange_every=int(w.exchange_every), series_capacity=0, log_capacity=0,
+                   schedule=int(schedule))
+    out = np.zeros(len(w.n_beads), dtype=np.int32)
+    stream = torch.cuda.current_stream()
+    _check(lib().pt_autotune(C.byref(model_struct(w.model)), C.byref(cfg), int(trial_sweeps),
+                             C.c_void_p(stream.cuda_stream), _ptr(out, C.c_int32)))
+    return out
+
+
 # ------------------------------------------------------------ convenience --
 
 class Simulation:
     """A workload on the GPU: workspace, handle and typed read-backs."""
 
     def __init__(self, w, precision: Optional[str] = None, series_capacity: int = 0,
-                 log_capacity: int = 0, device: str = "cuda", schedule: int = PT_SCHED_AUTO):
+                 log_capacity: int = 0, device: str = "cuda", schedule: int = PT_SCHED_AUTO,
+                 mapping=None):
         import torch
 
         self.w = w
@@ -226,6 +280,12 @@ class Simulation:
             seed=int(w.seed), precision=PT_MIXED if prec == "mixed" else PT_FP64,
             exchange_every=int(w.exchange_every), series_capacity=int(series_capacity),
             log_capacity=int(log_capacity), schedule=int(schedule))
+        self._map = None
+        if mapping is not None:
+            self._map = np.ascontiguousarray(mapping, dtype=np.int32)
+            if self._map.shape != (len(w.n_beads),):
+                raise ValueError("mapping needs one code per chain")
+            self.cfg.mapping = _ptr(self._map, C.c_int32)
         nbytes = pt_workspace_bytes(self.model, self.cfg)
         if nbytes == 0:
             _check(PT_EINVAL)
@@ -298,3 +358,14 @@ class Simulation:
     def mapping(self):
         """(beads per lane, wavefronts per replica, persistent flag) per chain."""
         return pt_get_mapping(self.h, len(self.w.n_beads))
+
+    def digests(self) -> np.ndarray:
+        """[slots, 2] uint64 decision digests (accept words, exchange outcomes)."""
+        return pt_get_digests(self.h, self.total)
+
+    def state(self) -> bytes:
+        """A checkpoint of the run (see pt_get_state)."""
+        return pt_get_state(self.h)
+
+    def set_state(self, state: bytes) -> None:
+        pt_set_state(self.h, state)

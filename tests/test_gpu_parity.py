@@ -34,12 +34,12 @@ def _pt():
     return pt
 
 
-def run_gpu(w, sweeps, precision, schedule=0, chunks=None):
+def run_gpu(w, sweeps, precision, schedule=0, chunks=None, mapping=None):
     """Runs the library; returns every observable state.  chunks splits the
     sweeps over several pt_sweep calls."""
     pt = _pt()
     sim = pt.Simulation(w, precision=precision, series_capacity=sweeps, log_capacity=sweeps,
-                        schedule=schedule)
+                        schedule=schedule, mapping=mapping)
     for n in (chunks or [sweeps]):
         sim.sweep(n)
     g = dict(coords=sim.coords(), energy=sim.energy(), obs=sim.observables(), series=sim.series())
@@ -290,3 +290,152 @@ def test_persistent_schedule_equals_per_sweep(case):
     b = run_gpu(w, sweeps, prec, schedule=2, chunks=chunks)
     assert np.all(a["persistent"] == 0) and np.all(b["persistent"] == 1)
     _assert_same_state(a, b)
+
+
+def test_thermodynamics_agree_with_oracle():
+    """Per-temperature <E> and C_V/N of the mixed GPU run (from its running
+    energies) lie within 2 sigma of the oracle's estimates, sigma being the
+    oracle's binned / jackknife error, on the full small-chain run; the device
+    accumulators agree with the series."""
+    from oracle import thermo as OT
+    from paper_1107_3490_amd import thermo as TH
+    pt = _pt()
+    w = I.named("c1")
+    print(f"\n[case] thermodynamics c1: slots={w.total_slots} sweeps={w.sweeps}", flush=True)
+    sim = pt.Simulation(w, precision="mixed", series_capacity=w.sweeps)
+    sim.sweep(w.sweeps)
+    ser, acc = sim.series(), sim.observables()["acc"]
+    sim.close()
+    orc = O.Simulation(w)
+    r = orc.run(w.sweeps, series=True)
+    nb = np.repeat(w.n_beads, w.n_slots)
+    p = TH.estimates(ser, w.betas, nb)
+    o = OT.estimates(r["series"], w.betas, nb)
+    for g in range(w.total_slots):
+        assert abs(p["E"][g] - o[g]["E"]) <= 2 * o[g]["dE"], (g, p["E"][g], o[g])
+        assert abs(p["Cv"][g] - o[g]["Cv"]) <= 2 * o[g]["dCv"], (g, p["Cv"][g], o[g])
+        assert abs(p["Rg2"][g] - o[g]["Rg2"]) <= 2 * o[g]["dRg2"], (g, p["Rg2"][g], o[g])
+    a = TH.from_accumulators(acc, w.betas, nb)
+    whole = TH.estimates(ser, w.betas, nb, burn_in=0.0, n_bins=25)
+    assert np.all(a["n"] == w.sweeps)
+    for k in ("E", "Rg2", "Ree2"):
+        assert np.allclose(a[k], whole[k], rtol=1e-10, atol=1e-12), k
+
+
+def _mix64(z):
+    m = (1 << 64) - 1
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def _digests_from_logs(w, alog, elog, e0=0):
+    """Per-slot digests written out from the decision logs (independent of the
+    library): accept words in order, then exchange outcomes of lower slots."""
+    S = w.total_slots
+    n_of = np.repeat(w.n_beads, w.n_slots)
+    words = (n_of + 63) // 64
+    off = np.concatenate([[0], np.cumsum(words)[:-1]])
+    d = np.zeros((S, 2), dtype=object)
+    d[:, :] = 0
+    for g in range(S):
+        for t in range(alog.shape[0]):
+            for j in range(words[g]):
+                d[g, 0] = _mix64(d[g, 0] ^ int(alog[t, off[g] + j]))
+        for e in range(elog.shape[0]):
+            if elog[e, g] != 255:
+                d[g, 1] = _mix64(d[g, 1] ^ (((e0 + e) << 1) | int(elog[e, g])))
+    return d.astype(np.uint64)
+
+
+def test_digests_fold_the_oracle_decisions():
+    """The device digests equal those folded from the oracle's logs, also for a
+    run that keeps no logs on the device."""
+    pt = _pt()
+    w = I.make_workload([40, 130], [6, 5], [(0.2, 1.5), (0.3, 1.0)], "walk", 61, 0, "mixed")
+    sweeps = 120
+    print(f"\n[case] digests: slots={w.total_slots} sweeps={sweeps}", flush=True)
+    orc = O.Simulation(w)
+    r = orc.run(sweeps, accept_log=True, exch_log=True)
+    want = _digests_from_logs(w, r["accept_log"], r["exch_log"])
+    for sched in (1, 2):
+        sim = pt.Simulation(w, precision="mixed", schedule=sched)
+        sim.sweep(sweeps)
+        got = sim.digests()
+        sim.close()
+        assert np.array_equal(got, want), sched
+
+
+def test_checkpoint_resume_is_exact():
+    """Save after 37 sweeps, restore into a new handle (other schedule and
+    precision), run 23 more: everything equals the uninterrupted run."""
+    pt = _pt()
+    w = I.make_workload([70, 33], [7, 4], [(0.2, 1.5), (0.3, 1.0)], "walk", 62, 0, "mixed",
+                        exchange_every=2)
+    print(f"\n[case] checkpoint: slots={w.total_slots}", flush=True)
+    a = pt.Simulation(w, precision="mixed", schedule=2)
+    a.sweep(37)
+    st = a.state()
+    a.sweep(23)
+    b = pt.Simulation(w, precision="fp64", schedule=1)
+    b.sweep(5)
+    b.set_state(st)
+    b.sweep(23)
+    oa, ob = a.observables(), b.observables()
+    assert np.array_equal(a.coords(), b.coords())
+    assert np.array_equal(a.digests(), b.digests())
+    assert np.array_equal(oa["perm"], ob["perm"])
+    assert (oa["t"], oa["e"]) == (ob["t"], ob["e"]) == (60, 30)
+    assert np.array_equal(oa["counts"][:, :3], ob["counts"][:, :3])
+    assert np.array_equal(a.energy(), b.energy())
+    # and the same decisions as the oracle
+    orc = O.Simulation(w)
+    orc.run(60)
+    assert np.array_equal(a.coords(), orc.coords) and np.array_equal(oa["perm"], orc.perm)
+    # a state of another batch is refused
+    w2 = I.make_workload([70, 33], [7, 4], [(0.2, 1.5), (0.3, 1.0)], "walk", 62, 0, "mixed")
+    w2.seed = w.seed + 1
+    c = pt.Simulation(w2)
+    with pytest.raises(pt.PtError) as ei:
+        c.set_state(st)
+    assert ei.value.code == pt.PT_EINVAL
+    with pytest.raises(pt.PtError):
+        b.set_state(b"\0" * len(st))
+    for s in (a, b, c):
+        s.close()
+
+
+@pytest.mark.parametrize("n,codes", [(100, [0x21, 0x12, 0x41, 0x22, 0x14]),
+                                     (300, [0x81, 0x42, 0x24, 0x44]),
+                                     (700, [0x82, 0x44, 0x84])])
+def test_results_do_not_depend_on_mapping(n, codes):
+    """Every (beads per lane, wavefronts) mapping of a chain, under both
+    schedules, gives bit-identical results (and the oracle's)."""
+    w = I.make_workload([n], [5], [(0.2, 2.0)], "walk", 70 + n, 0, "mixed")
+    sweeps = 12 if n < 500 else 4
+    print(f"\n[case] mappings N={n}: {[hex(c) for c in codes]}", flush=True)
+    ref = None
+    for code in codes:
+        for sched in (1, 2):
+            g = run_gpu(w, sweeps, "mixed", schedule=sched, mapping=[code])
+            if ref is None:
+                ref = g
+                o = O.Simulation(w)
+                o.run(sweeps)
+                assert np.array_equal(g["coords"], o.coords)
+            else:
+                _assert_same_state(ref, g)
+
+
+def test_autotune_picks_valid_mappings():
+    pt = _pt()
+    w = I.subset(I.named("c4"), [0, 1, 2, 3, 4, 5, 6, 7], slots=8)
+    print(f"\n[case] autotune: N={list(w.n_beads)}", flush=True)
+    codes = pt.autotune(w, "mixed", trial_sweeps=5)
+    print("  mapping", [hex(int(c)) for c in codes], flush=True)
+    for n, c in zip(w.n_beads, codes):
+        b, wv = int(c) >> 4, int(c) & 15
+        assert b in (1, 2, 4, 8) and wv in (1, 2, 4) and n <= 64 * b * wv < max(65, 4 * n)
+    a = run_gpu(w, 6, "mixed", mapping=codes)
+    d = run_gpu(w, 6, "mixed")
+    _assert_same_state(a, d)

@@ -105,3 +105,23 @@ def test_too_long_chain_and_small_workspace(L):
     assert rc == pt.PT_ENOMEM
     rc, msg = _init_rc(m, cfg, ws=0x100010, nbytes=need)
     assert rc == pt.PT_EINVAL and "aligned" in msg
+
+
+def test_mapping_override_is_validated(L):
+    m = pt.model_struct(I.model_params())
+    w = I.make_workload([100], [2], [(0.1, 1.5)], "straight", 1, 0, "fp64")
+    cfg, keep = _cfg(w)
+    base = pt.pt_workspace_bytes(m, cfg)
+    assert base > 0
+    for code, ok in ((0x21, True), (0x12, True), (0x14, True), (0x84, True), (0x11, False),
+                     (0x31, False), (0x23, False), (0x121, False), (-1, False)):
+        mp = np.array([code], dtype=np.int32)
+        cfg.mapping = pt._ptr(mp, C.c_int32)
+        n = L.pt_workspace_bytes(C.byref(m), C.byref(cfg))
+        assert (n > 0) == ok, (hex(code), n, L.pt_last_error())
+        if not ok:
+            assert "mapping" in L.pt_last_error().decode()
+    # a wider mapping pads the replica further: more workspace
+    mp = np.array([0x84], dtype=np.int32)
+    cfg.mapping = pt._ptr(mp, C.c_int32)
+    assert L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) > base

@@ -16,6 +16,7 @@ import numpy as np
 from scipy import integrate, special
 
 from oracle import oracle as O
+from oracle import thermo as OT
 from paper_1107_3490_amd import inputs as I
 
 M = I.model_params()
@@ -99,6 +100,9 @@ def _check(n, exact, seed, sweeps=300000, temps=(0.3, 2.5), slots=4):
         # second moment <E^2> = var + <E>^2 (specific heat, Eq. 7)
         m2, err2 = binned(e[:, g] ** 2)
         assert abs(m2 - (var + want * want)) < 4 * err2, (n, g, beta, m2, var + want * want)
+        # C_V/N = beta^2 var / N with its jackknife error (the oracle's estimator)
+        cv, dcv = OT.specific_heat(list(e[:, g]), beta, n, 50)
+        assert abs(cv - beta * beta * var / n) < 4 * dcv, (n, g, beta, cv, beta * beta * var / n, dcv)
 
 
 def test_two_bead_chain_matches_quadrature():
