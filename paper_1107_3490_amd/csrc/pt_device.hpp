@@ -111,42 +111,46 @@ __device__ __forceinline__ double fene64(const Consts &k, double r2) {
     return (y > 0.0) ? v : __builtin_inf();
 }
 
-// FP32 Lennard-Jones term from an FP64 separation, and b = s6^2 + s6 that
-// bounds its error.  With u = 2^-24 and relative errors to first order: the
-// conversions and the three roundings of r^2 give 5u; v_rcp_f32 (1 ulp, 2u),
-// the conversion of sigma^2 and the product give s2 within 9u; s4 19u; s6 29u;
-// fma(s6, s6, -s6) is within (|2 s6 - 1| 29u s6 + u |g|) <= 59u b; the final
-// fma and the conversions of 4 eps and E_LJ(rc) bring the term within
-// 61u (4 eps) b + 2u |E_LJ(rc)|, and the later FP32 difference of the new and
-// old terms adds u (4 eps) b + u |E_LJ(rc)| per term.  For a pair inside the
-// cutoff b >= b_rc = s6(rc)(1 + s6(rc)), so the |E_LJ(rc)| parts are below
-// c_erc u (4 eps) b, c_erc = 3 |E_LJ(rc)| / (4 eps b_rc).  A pair whose FP32
-// r^2 lands on the other side of the cutoff than the FP64 one is within 6u
-// rc^2 of it, where |E_mod| <= |dE/dr^2|(rc) 6u rc^2 = c_win u (4 eps) b_rc.
-// The kernels sum the FP32 pair terms t of a move in FP32 (in-lane tree,
-// butterfly and the tree over wavefronts: a pairwise tree of depth <= 11),
-// which adds at most 11.01u sum |t|; since |E_LJ(rc)| <= (4 eps) b for any
-// pair inside the cutoff, |t| <= 2 (4 eps)(b_new + b_old)(1 + 2^-20), so the
-// sum adds at most 22.1u (4 eps) per unit of b.  The host sets kbound =
-// kappa u (4 eps)(1 + 2^-8), kappa >= 62 + c_erc + c_win with a margin (at
-// least 128), plus 24 for the sum, and the kernels accumulate b over both
-// evaluations of every pair, inside or outside the cutoff; the FP32 sum of
-// the b (depth <= 11, at most 11.01u low) is scaled by 1 + 2^-20 before use.
+// FP32 Lennard-Jones term from an FP64 separation, and s6 = (sigma^2/r^2)^3,
+// whose b = s6^2 + s6 bounds the term's error.  r^2 is formed in FP64 from the
+// FP64 separation and rounded to FP32 once; beyond the cutoff r^2 is clamped
+// to the cutoff, where the term is zero up to the rounding of the shift, and
+// both evaluations of a far pair give the same value, so their difference is
+// an exact zero.  With u = 2^-24 and relative errors to first order: r^2 is
+// within 1.01u; v_rcp_f32 (1 ulp, 2u), the conversion of sigma^2 and the
+// product give s2 within 5u; s4 11u; s6 17u; fma(s6, s6, -s6) is within
+// (|2 s6 - 1| 17u s6 + u |g|) <= 35u b; the final fma and the conversions of
+// 4 eps and E_LJ(rc) bring the term within 37u (4 eps) b + 2u |E_LJ(rc)|, and
+// the later FP32 difference of the new and old terms adds u (4 eps) b +
+// u |E_LJ(rc)| per term.  For a pair inside the cutoff b >= b_rc =
+// s6(rc)(1 + s6(rc)), so the |E_LJ(rc)| parts are below c_erc u (4 eps) b,
+// c_erc = 3 |E_LJ(rc)| / (4 eps b_rc).  A pair whose FP32 r^2 lands on the
+// other side of the cutoff than the FP64 one is within 2u rc^2 of it, where
+// |E_mod| <= |dE/dr^2|(rc) 2u rc^2 <= c_win u (4 eps) b_rc (c_win is taken
+// for a 6u window).  The kernels sum the FP32 pair terms t of a move in FP32
+// (in-lane tree, butterfly and the tree over wavefronts: a pairwise tree of
+// depth <= 11), which adds at most 11.01u sum |t|; since |E_LJ(rc)| <=
+// (4 eps) b for any pair inside the cutoff, |t| <= 2 (4 eps)(b_new + b_old)
+// (1 + 2^-20), so the sum adds at most 22.1u (4 eps) per unit of b.  The host
+// sets kbound = kappa u (4 eps)(1 + 2^-8), kappa >= 62 + c_erc + c_win with
+// a margin (at least 128; the terms need 39 + c_erc + c_win), plus 24 for the
+// sum.  Per pair the kernels accumulate b' = S^2 + S with S = s6_new + s6_old,
+// which is >= b_new + b_old, inside or outside the cutoff; the FP32 sum of
+// the b' (depth <= 11, at most 11.01u low) is scaled by 1 + 2^-20 before use.
 struct Lj32 {
-    float e;  // term
-    float b;  // s6^2 + s6
+    float e;   // term
+    float s6;  // (sigma^2 / r^2)^3 of the (clamped) FP32 r^2
 };
 
 __device__ __forceinline__ Lj32 lj32(const Consts &k, double dx, double dy, double dz) {
-    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-    const float r2 = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
+    const double r2d = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    const float r2 = __builtin_fminf((float)r2d, k.rc2_f);
     const float q = __builtin_amdgcn_rcpf(r2);
     const float s2 = k.sig2_f * q;
     const float s6 = (s2 * s2) * s2;
-    const float e = __builtin_fmaf(k.four_eps_f, __builtin_fmaf(s6, s6, -s6), -k.e_rc_f);
     Lj32 o;
-    o.e = (r2 < k.rc2_f) ? e : 0.0f;
-    o.b = __builtin_fmaf(s6, s6, s6);
+    o.e = __builtin_fmaf(k.four_eps_f, __builtin_fmaf(s6, s6, -s6), -k.e_rc_f);
+    o.s6 = s6;
     return o;
 }
 

@@ -373,9 +373,13 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 const LeafMx s = lane_tree<0, B>([&](int b) {
                     const Lj32 pn = lj32(K, rx[b] - xn, ry[b] - yn, rz[b] - zn);
                     const Lj32 po = lj32(K, rx[b] - xo, ry[b] - yo, rz[b] - zo);
-                    const bool self = mine && b == slot;
-                    const float tt = self ? 0.0f : pn.e - po.e;
-                    const float bb = self ? 0.0f : pn.b + po.b;
+                    // The moved bead's own leaf and padding leaves are zeros (a
+                    // padding bead's two terms are equal; its bound is dropped so
+                    // that the bound does not depend on the padding).
+                    const bool skip = (mine && b == slot) || tid * B + b >= n;
+                    const float sb = pn.s6 + po.s6;
+                    const float tt = skip ? 0.0f : pn.e - po.e;
+                    const float bb = skip ? 0.0f : __builtin_fmaf(sb, sb, sb);
                     return LeafMx{tt, bb};
                 });
                 double sm = (double)wave_tree(s.t);
@@ -861,7 +865,7 @@ __global__ void k_selftest(const Consts k, int op, const double *x, const double
         case 5: {
             const Lj32 r = lj32(k, x[i], y[i], 0.0);
             out[2 * i] = (double)r.e;
-            out[2 * i + 1] = k.kbound * (double)r.b;
+            out[2 * i + 1] = k.kbound * (double)__builtin_fmaf(r.s6, r.s6, r.s6);
             break;
         }
         case 6: {
