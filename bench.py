@@ -16,6 +16,7 @@ Prints one JSON line.  Default workload: one chain of N = 100 monomers,
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -48,6 +49,7 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     sim = pt.Simulation(w, precision=precision, schedule=schedule, mapping=mapping)
     bpl, wpr, _ = sim.mapping()
     tuned = sorted({(int(n), int(b), int(v)) for n, b, v in zip(w.n_beads, bpl, wpr)})
+    classes = sorted({(int(b), int(v)) for b, v in zip(bpl, wpr)})
     persistent = bool(np.all(sim.mapping()[2] == 1))
     sim.sweep(warmup)
     torch.cuda.synchronize()
@@ -61,7 +63,32 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     return dict(pairs=pairs, wall_s=wall, event_total_ms=total_ms, sweep_kernel_ms=sweep_ms,
                 launches=launches, rescored=int(obs["counts"][:, 3].sum()),
                 moves=int(obs["counts"][:, 5].sum()), exch_recompute=int(obs["counts"][:, 4].sum()),
-                persistent=persistent, mapping=tuned)
+                persistent=persistent, mapping=tuned, classes=classes,
+                resyncs=int(obs["counts"][:, 6].sum()))
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for fn in ("paper_1107_3490_amd/csrc/pt_kernels.hip", "paper_1107_3490_amd/csrc/pt_device.hpp",
+               "paper_1107_3490_amd/csrc/pt_internal.hpp"):
+        with open(os.path.join(ROOT, fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel, sweeps_per_launch):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (copy-calibrated, per sweep), or None when they were
+    taken on other kernel sources or another kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(workload)
+    if e is None or e.get("kernel") != kernel or t.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return (e["read_bytes_per_sweep"] + e["write_bytes_per_sweep"]) * sweeps_per_launch
 
 
 def with_transfers(w, steps):
@@ -149,6 +176,13 @@ def main():
     flop_per_launch = FLOP_PER_PAIR * w.pair_interactions_per_sweep() * args.steps / mixed["launches"]
     achieved = flop_per_launch / avg_kernel_s
     fp64_value = fp64["pairs"] / (fp64["event_total_ms"] / 1e3)
+    # The dominant kernel: the one class of the workload, or the most expensive one.
+    b_, w_ = max(mixed["classes"], key=lambda c: c[0] * c[1])
+    kernel = f"{'k_run' if mixed['persistent'] else 'k_sweep'}<{b_}, {w_}, true>"
+    # SIMDs a sweep can keep busy: one wavefront per SIMD at most for each of
+    # the W wavefronts of every replica (the latency-bound regime).
+    waves_of_n = {int(n): int(wv) for n, _, wv in mixed["mapping"]}
+    occupied = min(1024, sum(int(r) * waves_of_n[int(n)] for n, r in zip(w.n_beads, w.n_slots)))
     fp64_sweep_s = fp64["sweep_kernel_ms"] / 1e3 / args.steps
 
     out = {
@@ -173,6 +207,7 @@ def main():
         "replica_sweeps_per_s": args.steps * slots / (mixed["event_total_ms"] / 1e3),
         "wall_s": mixed["wall_s"],
         "rescored_moves": mixed["rescored"],
+        "energy_resyncs": mixed["resyncs"],
         "moves": mixed["moves"],
         "exchange_fp64_recomputes": mixed["exch_recompute"],
         "fp64_path": {
@@ -187,12 +222,15 @@ def main():
         "mixed_over_fp64": value / fp64_value,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_run (mixed, persistent)" if mixed["persistent"] else "k_sweep (mixed)",
+            "kernel": kernel,
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, kernel, args.steps / mixed["launches"]),
+            "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 FETCH_SIZE/WRITE_SIZE x copy calibration)",
+            "occupied_simds": occupied,
+            "frac_of_occupied_simds": achieved / (PEAK_FP32 * occupied / 1024.0),
             "avg_launch_ms": avg_kernel_s * 1e3,
             "flop_per_launch": flop_per_launch,
         },
