@@ -437,12 +437,15 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                     Y[ak] = yn;
                     Z[ak] = zn;
                 }
+                // Only the wavefront holding bead k has a register to update.
+                if (W == 1 || __builtin_amdgcn_readfirstlane(wv) == (owner >> 6)) {
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool me = mine && b == slot;
-                    rx[b] = me ? xn : rx[b];
-                    ry[b] = me ? yn : ry[b];
-                    rz[b] = me ? zn : rz[b];
+                    for (int b = 0; b < B; ++b) {
+                        const bool me = mine && b == slot;
+                        rx[b] = me ? xn : rx[b];
+                        ry[b] = me ? yn : ry[b];
+                        rz[b] = me ? zn : rz[b];
+                    }
                 }
                 E = E + de_used;
                 Bd = Bd + bm + 0x1p-52 * dabs(E);
