@@ -75,3 +75,55 @@ def from_accumulators(acc: np.ndarray, betas, n_beads) -> dict:
     e = a[:, 1] / n
     return {"E": e, "Cv": beta * beta * (a[:, 2] / n - e * e) / np.asarray(n_beads, dtype=np.float64),
             "Rg2": a[:, 3] / n, "Ree2": a[:, 4] / n, "n": n}
+
+
+def scan(n_beads: int, t_min: float, t_max: float, slots: int, sweeps: int, seed: int = 1,
+         precision: str = "mixed", start: str = "straight", burn_in: float = 0.2, n_bins: int = 32,
+         step_edge: float = 0.2, chunk: int = 100000) -> dict:
+    """Parallel-tempering run of one chain on the GPU (geometric ladder
+    [t_min, t_max], exchange after every sweep) and its per-temperature
+    estimates; adds T = 1/beta.  The series is kept on the device for all
+    sweeps (sweeps x slots x 24 bytes)."""
+    from . import inputs as I
+    from . import pt
+
+    w = I.make_workload([n_beads], [slots], [(t_min, t_max)], start, seed, sweeps, precision,
+                        step_edge=step_edge)
+    sim = pt.Simulation(w, precision=precision, series_capacity=sweeps)
+    done = 0
+    while done < sweeps:
+        n = min(chunk, sweeps - done)
+        sim.sweep(n)
+        done += n
+    ser = sim.series()
+    sim.close()
+    out = estimates(ser, w.betas, [n_beads] * slots, burn_in=burn_in, n_bins=n_bins)
+    out["T"] = 1.0 / np.asarray(w.betas)
+    return out
+
+
+def main(argv=None):
+    """python -m paper_1107_3490_amd.thermo --n 13 --tmin 0.1 --tmax 2.5 --slots 64 --sweeps 200000"""
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="per-temperature thermodynamics of one chain (GPU)")
+    ap.add_argument("--n", type=int, default=13)
+    ap.add_argument("--tmin", type=float, default=0.1)
+    ap.add_argument("--tmax", type=float, default=2.5)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--sweeps", type=int, default=200000)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--burn-in", type=float, default=0.2)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    a = ap.parse_args(argv)
+    r = scan(a.n, a.tmin, a.tmax, a.slots, a.sweeps, seed=a.seed, precision=a.precision, burn_in=a.burn_in)
+    i, j = int(np.argmax(r["Cv"])), int(np.argmax(r["dRg2dT"]))
+    print(json.dumps({"N": a.n, "Cv_peak_T": float(r["T"][i]), "dRg2dT_peak_T": float(r["T"][j])}))
+    for k in range(len(r["T"])):
+        print(f"T={r['T'][k]:.4f}  E={r['E'][k]:.4f}+-{r['dE'][k]:.4f}  Cv/N={r['Cv'][k]:.4f}+-{r['dCv'][k]:.4f}"
+              f"  Rg2={r['Rg2'][k]:.4f}  dRg2/dT={r['dRg2dT'][k]:.4f}+-{r['ddRg2dT'][k]:.4f}")
+
+
+if __name__ == "__main__":
+    main()

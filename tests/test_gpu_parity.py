@@ -439,3 +439,18 @@ def test_autotune_picks_valid_mappings():
     a = run_gpu(w, 6, "mixed", mapping=codes)
     d = run_gpu(w, 6, "mixed")
     _assert_same_state(a, d)
+
+
+def test_thirteen_bead_transitions_where_the_paper_has_them():
+    """Whole-path physics check (qualitative, no closed form): a parallel-
+    tempering run of N = 13 puts the specific-heat peak (freezing) near
+    T = 0.33 and the peak of d<R_gyr^2>/dT (collapse) near T = 1.0, as the
+    paper reports for this chain (Sec. 4)."""
+    from paper_1107_3490_amd import thermo as TH
+    print("\n[case] N=13 thermodynamics, 64 slots, 100000 sweeps", flush=True)
+    r = TH.scan(13, 0.1, 2.5, 64, 100000, seed=7)
+    t_cv = r["T"][int(np.argmax(r["Cv"]))]
+    t_rg = r["T"][int(np.argmax(r["dRg2dT"]))]
+    print(f"  C_V peak at T={t_cv:.3f}, d<Rg2>/dT peak at T={t_rg:.3f}", flush=True)
+    assert 0.26 <= t_cv <= 0.40
+    assert 0.75 <= t_rg <= 1.25
