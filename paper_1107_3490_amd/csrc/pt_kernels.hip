@@ -397,18 +397,16 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 const double dem = sm + df;
                 const double bt = bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem);
                 const double lo = dem - bt, hi = dem + bt;
-                const bool sure_acc = (hi <= 0.0) || (beta * hi < th);
-                const bool sure_rej = (lo > 0.0) && !(beta * lo < th);
-                if (df == __builtin_inf()) {
-                    acc = false;  // a broken bond is rejected whatever the pair sum
-                } else if (finite(bt) && finite(dem) && (sure_acc || sure_rej)) {
-                    acc = sure_acc;
-                    de_used = dem;
-                    bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
-                } else {
-                    exact = true;
-                    ++n_rescore;
-                }
+                // Straight-line: every outcome is computed, one is kept.
+                const bool sure_acc = (hi <= 0.0) | (beta * hi < th);
+                const bool sure_rej = (lo > 0.0) & !(beta * lo < th);
+                const bool broken = df == __builtin_inf();  // rejected whatever the pair sum
+                const bool sure = broken | (finite(bt) & finite(dem) & (sure_acc | sure_rej));
+                acc = !broken & sure_acc;
+                de_used = dem;
+                bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
+                exact = __builtin_amdgcn_readfirstlane(sure ? 0 : 1) != 0;
+                n_rescore += exact ? 1 : 0;
             }
             if (exact) {
                 const Leaf64 s = lane_tree<0, B>(leaf64);
@@ -430,7 +428,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 de_used = de;
                 bm = bound64(log2c(n), ab, dfl, dfr, de);
             }
-            if (acc) {
+            if (__builtin_amdgcn_readfirstlane(acc ? 1 : 0) != 0) {
                 if (mine) {
                     const int ak = G::pos(k);
                     X[ak] = xn;

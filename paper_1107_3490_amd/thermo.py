@@ -118,8 +118,11 @@ def main(argv=None):
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     a = ap.parse_args(argv)
     r = scan(a.n, a.tmin, a.tmax, a.slots, a.sweeps, seed=a.seed, precision=a.precision, burn_in=a.burn_in)
-    i, j = int(np.argmax(r["Cv"])), int(np.argmax(r["dRg2dT"]))
-    print(json.dumps({"N": a.n, "Cv_peak_T": float(r["T"][i]), "dRg2dT_peak_T": float(r["T"][j])}))
+    i = int(np.argmax(r["Cv"]))
+    # d<R_gyr^2>/dT peaks at freezing too; report the peak above twice the C_V peak.
+    hot = np.nonzero(r["T"] > 2 * r["T"][i])[0]
+    j = int(hot[np.argmax(r["dRg2dT"][hot])]) if hot.size else int(np.argmax(r["dRg2dT"]))
+    print(json.dumps({"N": a.n, "Cv_peak_T": float(r["T"][i]), "dRg2dT_peak_T_above_freezing": float(r["T"][j])}))
     for k in range(len(r["T"])):
         print(f"T={r['T'][k]:.4f}  E={r['E'][k]:.4f}+-{r['dE'][k]:.4f}  Cv/N={r['Cv'][k]:.4f}+-{r['dCv'][k]:.4f}"
               f"  Rg2={r['Rg2'][k]:.4f}  dRg2/dT={r['dRg2dT'][k]:.4f}+-{r['ddRg2dT'][k]:.4f}")
