@@ -240,7 +240,10 @@ __device__ __forceinline__ int log2c(int n) { return 32 - __builtin_clz((unsigne
 // per-wavefront partial sums (double-buffered over consecutive moves).
 template <int B, int W>
 struct SweepLds {
-    static constexpr int MB = (Geo<B, W>::NP >= 2048) ? 32 : 64;  // moves per batch (LDS budget)
+    // Moves per batch: 32 at the LDS budget of 2048 beads, and for short
+    // chains, where an accepted move more often touches a later move's
+    // bonds (which then recomputes them); 64 otherwise.
+    static constexpr int MB = (Geo<B, W>::NP >= 2048 || Geo<B, W>::NP <= 128) ? 32 : 64;
     double xyz[3 * Geo<B, W>::NP];
     MoveRec rec[MB];
     double part[2][2][W];
