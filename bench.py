@@ -132,6 +132,52 @@ def cpu_baseline(w, budget_s=12.0, threads=None):
                        f"{dt:.1f} s, OpenMP over slots, FP64 incl. per-sweep canonical energy)")
 
 
+def paper_protocol(n_beads=55, sweeps=4000, every=1000, edge=0.02,
+                   replicas=(1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)):
+    """The benchmark of the paper's Sec. 5 on this GPU: one chain of N = 55,
+    displacement edge 0.02, 4000 sweeps, an exchange step every 1000 sweeps, as
+    a function of the number of replicas n_r.  t_GPU includes set-up, the
+    host-to-device copies, the sweeps and the read-back of every conformation
+    (the paper's timing includes its copies); S_p = t_CPU / t_GPU with t_CPU the
+    oracle on one core, timed on a few replicas and scaled by n_r (its cost is
+    linear in n_r).  Context only: the paper's hardware and numbers differ."""
+    import torch
+    from oracle import oracle as O
+    from paper_1107_3490_amd import inputs as I
+    from paper_1107_3490_amd import pt
+
+    def workload(nr):
+        return I.make_workload([n_beads], [nr], [(0.1, 1.5)], "straight", 55, sweeps, "mixed",
+                               name="paper-protocol", step_edge=edge, exchange_every=every)
+
+    # one oracle core: 4 replicas, 1000 sweeps
+    wc = workload(4)
+    sim = O.Simulation(wc, n_threads=1)
+    t0 = time.perf_counter()
+    sim.run(1000)
+    cpu_per_replica_sweep = (time.perf_counter() - t0) / (4 * 1000)
+    rows = []
+    for nr in replicas:
+        w = workload(nr)
+        for prec in ("mixed", "fp64"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = pt.Simulation(w, precision=prec)
+            s.sweep(sweeps)
+            s.coords()
+            s.observables()
+            torch.cuda.synchronize()
+            t_gpu = time.perf_counter() - t0
+            s.close()
+            t_cpu = cpu_per_replica_sweep * nr * sweeps
+            rows.append({"n_r": nr, "precision": prec, "t_gpu_s": t_gpu, "t_cpu_1core_s": t_cpu,
+                         "S_p": t_cpu / t_gpu,
+                         "pair_per_s": w.pair_interactions_per_sweep() * sweeps / t_gpu})
+    return {"protocol": f"N={n_beads}, edge {edge}, {sweeps} sweeps, exchange every {every}, "
+                        "straight start, T geometric in [0.1, 1.5]; t_GPU incl. set-up, copies, read-back",
+            "cpu_1core_s_per_replica_sweep": cpu_per_replica_sweep, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +190,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default mapping instead of the autotuner's")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--paper-protocol", action="store_true",
+                    help="the paper's benchmark: N = 55, edge 0.02, 4000 sweeps, exchange every 1000, "
+                         "replica-count scan with speed-ups over one oracle core")
     args = ap.parse_args()
+    if args.paper_protocol:
+        print(json.dumps(paper_protocol()), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         n = 256 * 1024 * 1024 // 4
@@ -156,8 +208,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of chains and ladders is described in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding chains and "
+              "ladders over GPUs is designed but not built in this library.", file=sys.stderr)
         sys.exit(2)
 
     from paper_1107_3490_amd import inputs as I
