@@ -322,8 +322,14 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
         // wavefront, this one possibly not yet to the other wavefronts.
         int last_k = -1;
         double lx = 0.0, ly = 0.0, lz = 0.0;
+        // With one wavefront per replica the next move's record is read one
+        // move ahead (its LDS latency then overlaps the current move); with
+        // more, the registers are worth more than the latency.
+        constexpr bool AHEAD = (W == 1);
+        MoveRec rnext = S.rec[0];
         for (int i = 0; i < nb; ++i) {
-            const MoveRec r = S.rec[i];
+            const MoveRec r = AHEAD ? rnext : S.rec[i];
+            if constexpr (AHEAD) rnext = S.rec[(i + 1 < MB) ? i + 1 : MB - 1];
             const int k = __builtin_amdgcn_readfirstlane(r.k);
             const uint64_t cf =
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r.conflict)) |
