@@ -217,6 +217,13 @@ PT_API size_t pt_state_bytes(pt_handle *h);
 PT_API int pt_get_state(pt_handle *h, void *h_buf, size_t bytes);
 PT_API int pt_set_state(pt_handle *h, const void *h_buf, size_t bytes);
 
+/* Test hook: the number of polls (each a short sleep, about 2^24 by default:
+ * seconds) after which a persistent run's wait for an exchange partner gives
+ * up.  A small value makes every wait whose partner has not arrived yet time
+ * out, which exercises the failure path (PT_EHIP, then PT_ESTATE until
+ * pt_set_state) while every block still exits.  Applies to later launches. */
+PT_API int pt_set_spin_limit(pt_handle *h, uint32_t polls);
+
 /* Timing of the sweep kernels: runs n sweeps like pt_sweep, with HIP events
  * recorded on the handle's stream around every sweep-kernel launch (a
  * persistent launch covers all n sweeps and their exchange steps), then

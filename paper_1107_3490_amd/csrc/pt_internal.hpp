@@ -65,6 +65,7 @@ struct Tables {
     int64_t series_cap;
     int32_t total_slots;
     int32_t exchange_every;
+    uint32_t spin_limit;         // polls of a persistent run's partner wait before it gives up
     uint64_t seed;
     Consts k;
 };

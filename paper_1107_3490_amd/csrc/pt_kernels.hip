@@ -693,8 +693,8 @@ __global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *
 // ---------------------------------------------------------- persistent run --
 // Spin (one thread) until *p >= v; false after a timeout or when another block
 // reported one, which also ends the waiting of every other block.
-__device__ __forceinline__ bool wait_ge(const int64_t *p, int64_t v, int32_t *err) {
-    for (uint32_t it = 0; it < (1u << 24); ++it) {
+__device__ __forceinline__ bool wait_ge(const int64_t *p, int64_t v, int32_t *err, uint32_t limit) {
+    for (uint32_t it = 0; it < limit; ++it) {
         if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         __builtin_amdgcn_s_sleep(2);
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
         if (tid < 64) {
             int32_t ok = 1, slot = g;
             if (lower) {
-                if (tid == 0) ok = wait_ge(&T.done[g + 1], t64 + 1, T.err) ? 1 : 0;
+                if (tid == 0) ok = wait_ge(&T.done[g + 1], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
                 ok = __builtin_amdgcn_readfirstlane(ok);
                 if (ok) {
                     __threadfence();
@@ -799,7 +799,7 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
                     slot = acc ? g + 1 : g;
                 }
             } else if (upper) {
-                if (tid == 0) ok = wait_ge(&T.dec[g], t64 + 1, T.err) ? 1 : 0;
+                if (tid == 0) ok = wait_ge(&T.dec[g], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
                 ok = __builtin_amdgcn_readfirstlane(ok);
                 if (ok) {
                     __threadfence();

@@ -389,6 +389,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.series_cap = L.series_cap;
     T.total_slots = S;
     T.exchange_every = cfg->exchange_every;
+    T.spin_limit = 1u << 24;
     T.seed = cfg->seed;
     T.k = k;
     h->d_tmp = (double *)(w + L.o_tmp);
@@ -979,5 +980,11 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
         }
         for (int c : chains) out[c] = best;
     }
+    return PT_OK;
+}
+
+PT_API int pt_set_spin_limit(pt_handle *h, uint32_t polls) {
+    if (h == nullptr || polls < 1) return fail(PT_EINVAL, "NULL handle or zero polls");
+    h->T.spin_limit = polls;
     return PT_OK;
 }

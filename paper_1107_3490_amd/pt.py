@@ -31,7 +31,7 @@ OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE3
 EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_autotune", "pt_sweep", "pt_exchange", "pt_energy",
            "pt_observables", "pt_reset_observables", "pt_get_coords", "pt_get_running",
            "pt_get_series", "pt_get_logs", "pt_get_digests", "pt_state_bytes", "pt_get_state",
-           "pt_set_state", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
+           "pt_set_state", "pt_set_spin_limit", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
            "pt_last_error")
 
 
@@ -87,6 +87,7 @@ def lib():
         L.pt_state_bytes.restype = C.c_size_t
         L.pt_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.pt_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.pt_set_spin_limit.argtypes = [C.c_void_p, C.c_uint32]
         L.pt_selftest.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), C.c_int64]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_destroy.restype = None
@@ -369,3 +370,7 @@ class Simulation:
 
     def set_state(self, state: bytes) -> None:
         pt_set_state(self.h, state)
+
+    def set_spin_limit(self, polls: int) -> None:
+        """Test hook for the persistent schedule's bounded partner waits."""
+        _check(lib().pt_set_spin_limit(C.c_void_p(self.h), int(polls)))

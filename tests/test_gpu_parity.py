@@ -457,3 +457,33 @@ def test_thirteen_bead_transitions_where_the_paper_has_them():
     print(f"  C_V peak at T={t_cv:.3f}, d<Rg2>/dT peak at T={t_rg:.3f}", flush=True)
     assert 0.26 <= t_cv <= 0.40
     assert 0.75 <= t_rg <= 1.25
+
+
+def test_persistent_wait_timeout_fails_cleanly_and_recovers():
+    """A persistent run whose partner waits give up after one poll: every block
+    still exits, the next synchronising call reports PT_EHIP, further sweeps
+    PT_ESTATE, and loading a saved state restores a run that goes on exactly
+    like an undisturbed one."""
+    pt = _pt()
+    w = I.make_workload([60], [16], [(0.2, 1.5)], "walk", 63, 0, "mixed")
+    print("\n[case] persistent timeout, 16 slots, spin limit 1", flush=True)
+    ref = pt.Simulation(w, schedule=2)
+    ref.sweep(30)
+    a = pt.Simulation(w, schedule=2)
+    a.sweep(10)
+    st = a.state()
+    a.set_spin_limit(1)
+    a.sweep(20)
+    with pytest.raises(pt.PtError) as ei:
+        a.energy()
+    assert ei.value.code == pt.PT_EHIP
+    with pytest.raises(pt.PtError) as ei:
+        a.sweep(1)
+    assert ei.value.code == pt.PT_ESTATE
+    a.set_spin_limit(1 << 24)
+    a.set_state(st)
+    a.sweep(20)
+    assert np.array_equal(a.coords(), ref.coords())
+    assert np.array_equal(a.digests(), ref.digests())
+    a.close()
+    ref.close()
