@@ -37,10 +37,12 @@
  *   u = (v0+.5)2^-32;
  *   exchange of slots (i,i+1) of stream chain c at step e: counter (i,e,c,2).
  * PT_FP64 evaluates the pair terms in that order.  PT_MIXED evaluates them in
- * FP32 from FP64 separations, sums in FP64, and re-scores in the FP64 order
- * every decision that a rigorous error bound cannot settle; its running
- * energies carry that bound and are re-synchronised with the FP64 energy
- * whenever an exchange decision needs it.  At the end of a sweep the running
+ * FP32 from r^2 formed in FP64 from FP64 separations (r^2 clamped at the
+ * cutoff), sums them in FP32 as the same pairwise tree (so every output is
+ * independent of the mapping), adds the FP64 bond terms in FP64, and re-scores
+ * in the FP64 order every decision that a rigorous error bound cannot settle;
+ * its running energies carry that bound and are re-synchronised with the FP64
+ * energy whenever an exchange decision needs it.  At the end of a sweep the running
  * energy is replaced by the FP64-order energy when its bound exceeds 2^-40
  * (PT_FP64) or 2^-10 (PT_MIXED) of max(1, |E|).
  *
