@@ -188,7 +188,11 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
  * that length (their own slots, ladders, coordinates, precision and
  * schedule) over trial_sweeps sweeps after a warm-up, in a device workspace of
  * its own on hip_stream, and writes the fastest as 16 B + W to
- * mapping_out[n_chains] (ready for config.mapping).  The caller's state is not
+ * mapping_out[n_chains] (ready for config.mapping).  Unless the schedule is
+ * PT_SCHED_PER_SWEEP it then merges classes greedily -- all chains of one
+ * mapping moved to a wider one that holds them -- while the whole batch,
+ * timed the same way, gets at least 2% faster and every class still runs
+ * persistently (persistent classes run one after another).  The caller's state is not
  * touched; results of a run do not depend on the mapping.  Synchronous.
  * Errors: as pt_init, and PT_ENOMEM when the device has no room. */
 PT_API int pt_autotune(const pt_model *model, const pt_config *config, int32_t trial_sweeps,

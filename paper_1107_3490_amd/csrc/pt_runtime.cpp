@@ -980,6 +980,65 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
         }
         for (int c : chains) out[c] = best;
     }
+    // Persistent classes run one after another, each for all sweeps, so a
+    // class whose chains finish early only adds its time.  Moving a class into
+    // a wider one that runs longer hides it, as long as the merged class still
+    // fits on the device at once: greedy merges, timed on the whole batch.
+    if (cfg->schedule != PT_SCHED_PER_SWEEP) {
+        pt_config t = *cfg;
+        t.series_capacity = 0;
+        t.log_capacity = 0;
+        std::vector<int32_t> mp(out, out + C);
+        // Whole-batch time of a mapping; *ok = every chain runs persistently.
+        auto time_batch = [&](const std::vector<int32_t> &m, double *ms, bool *ok) -> int {
+            t.mapping = m.data();
+            const size_t bytes = plan(&t).bytes;
+            void *ws = nullptr;
+            if (hipMalloc(&ws, bytes) != hipSuccess) return fail(PT_ENOMEM, "autotune: no room for %zu bytes", bytes);
+            pt_handle *h = nullptr;
+            int r = pt_init(model, &t, ws, bytes, hip_stream, &h);
+            *ok = r == PT_OK;
+            for (int c = 0; r == PT_OK && c < C; ++c) *ok = *ok && h->L.bpl[c] == (m[c] >> 4);
+            if (r == PT_OK)
+                for (const Class &cl : h->classes) *ok = *ok && cl.persistent;
+            if (r == PT_OK) r = pt_sweep(h, std::min<int64_t>(trial_sweeps, 4));
+            if (r == PT_OK) r = pt_time_sweeps(h, trial_sweeps, nullptr, ms, nullptr);
+            if (h) pt_destroy(h);
+            (void)hipFree(ws);
+            return r;
+        };
+        double cur_ms = 0.0;
+        bool ok = false;
+        rc = time_batch(mp, &cur_ms, &ok);
+        if (rc != PT_OK) return rc;
+        for (int round = 0; ok && round < 8; ++round) {
+            std::map<int, int> max_n;  // code -> longest chain in that class
+            for (int c = 0; c < C; ++c) max_n[mp[c]] = std::max(max_n[mp[c]], cfg->n_beads[c]);
+            if (max_n.size() < 2) break;
+            std::vector<int32_t> best_mp;
+            double best_ms = cur_ms * 0.98;  // a merge must gain at least 2%
+            for (auto &x : max_n)
+                for (auto &y : max_n) {
+                    const int cy = y.first;
+                    if (x.first == cy || 64 * (cy & 15) * (cy >> 4) < x.second) continue;
+                    std::vector<int32_t> cand = mp;
+                    for (int c = 0; c < C; ++c)
+                        if (cand[c] == x.first) cand[c] = cy;
+                    double ms = 0.0;
+                    bool fits = false;
+                    rc = time_batch(cand, &ms, &fits);
+                    if (rc != PT_OK) return rc;
+                    if (fits && ms < best_ms) {
+                        best_ms = ms;
+                        best_mp = cand;
+                    }
+                }
+            if (best_mp.empty()) break;
+            mp = best_mp;
+            cur_ms = best_ms;
+        }
+        std::copy(mp.begin(), mp.end(), out);
+    }
     return PT_OK;
 }
 
