@@ -48,7 +48,9 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     mapping = pt.autotune(w, precision, schedule, trial_sweeps=20) if tune else None
     sim = pt.Simulation(w, precision=precision, schedule=schedule, mapping=mapping)
     bpl, wpr, _ = sim.mapping()
-    tuned = sorted({(int(n), int(b), int(v)) for n, b, v in zip(w.n_beads, bpl, wpr)})
+    codes = list(mapping) if mapping is not None else [0] * len(w.n_beads)
+    tuned = sorted({(int(n), int(b), int(v)) + (("lane",) if int(c) & pt.PT_MAP_LANE else ())
+                    for n, b, v, c in zip(w.n_beads, bpl, wpr, codes)})
     classes = sorted({(int(b), int(v)) for b, v in zip(bpl, wpr)})
     persistent = bool(np.all(sim.mapping()[2] == 1))
     sim.sweep(warmup)
@@ -178,6 +180,55 @@ def paper_protocol(n_beads=55, sweeps=4000, every=1000, edge=0.02,
             "cpu_1core_s_per_replica_sweep": cpu_per_replica_sweep, "rows": rows}
 
 
+def ablations(sweeps=40, warmup=5):
+    """The paper's alternative designs, timed on this GPU beside the main path
+    (sweep-kernel event time, same inputs, identical results):
+      * one lane per replica (the paper's first design: a thread runs a whole
+        sweep) against the wavefront-per-replica kernels, FP64, on the paper's
+        N = 55 chain as a function of the number of replicas;
+      * the full FP64-order energy recomputed after every sweep (the paper's
+        per-sweep energy) against the running energy, on the N = 100 and
+        N = 500 workloads and the N = 55 chain at 4096 replicas."""
+    import torch
+    from paper_1107_3490_amd import inputs as I
+    from paper_1107_3490_amd import pt
+
+    def timed(w, prec, schedule=0, mapping=None):
+        s = pt.Simulation(w, precision=prec, schedule=schedule, mapping=mapping)
+        s.sweep(warmup)
+        torch.cuda.synchronize()
+        _, total_ms, _ = s.time_sweeps(sweeps)
+        persistent = bool(np.all(s.mapping()[2] == 1))
+        s.close()
+        return total_ms / sweeps, persistent
+
+    def chain55(nr):
+        return I.make_workload([55], [nr], [(0.1, 1.5)], "straight", 55, sweeps, "fp64",
+                               name="N=55", step_edge=0.02)
+
+    lane_rows = []
+    for nr in (64, 256, 1024, 4096, 16384):
+        w = chain55(nr)
+        wave_ms, pers = timed(w, "fp64")
+        lane_ms, _ = timed(w, "fp64", mapping=[pt.PT_MAP_LANE | 0x11])
+        pps = w.pair_interactions_per_sweep() * 1e3
+        lane_rows.append({"n_r": nr, "wavefront_ms_per_sweep": wave_ms, "wavefront_persistent": pers,
+                          "lane_ms_per_sweep": lane_ms, "wavefront_pair_per_s": pps / wave_ms,
+                          "lane_pair_per_s": pps / lane_ms, "lane_over_wavefront_time": lane_ms / wave_ms})
+    energy_rows = []
+    for name, w in (("c2", I.named("c2")), ("c3", I.named("c3")), ("N=55 x 4096", chain55(4096))):
+        for prec in ("mixed", "fp64"):
+            run_ms, pers = timed(w, prec)
+            full_ms, _ = timed(w, prec, schedule=pt.PT_SCHED_FULL_ENERGY)
+            energy_rows.append({"workload": name, "precision": prec, "persistent": pers,
+                                "running_energy_ms_per_sweep": run_ms,
+                                "full_energy_ms_per_sweep": full_ms,
+                                "full_over_running": full_ms / run_ms})
+    return {"ablations": "paper's alternative designs vs this library's, one MI355X, identical results",
+            "sweeps": sweeps, "one_lane_per_replica_fp64_N55_edge0.02": lane_rows,
+            "full_energy_every_sweep": energy_rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,7 +244,13 @@ def main():
     ap.add_argument("--paper-protocol", action="store_true",
                     help="the paper's benchmark: N = 55, edge 0.02, 4000 sweeps, exchange every 1000, "
                          "replica-count scan with speed-ups over one oracle core")
+    ap.add_argument("--ablations", action="store_true",
+                    help="the paper's alternative designs (one lane per replica, full energy every "
+                         "sweep) timed beside this library's")
     args = ap.parse_args()
+    if args.ablations:
+        print(json.dumps(ablations()), flush=True)
+        return
     if args.paper_protocol:
         print(json.dumps(paper_protocol()), flush=True)
         return
@@ -233,7 +290,7 @@ def main():
     kernel = f"{'k_run' if mixed['persistent'] else 'k_sweep'}<{b_}, {w_}, true>"
     # SIMDs a sweep can keep busy: one wavefront per SIMD at most for each of
     # the W wavefronts of every replica (the latency-bound regime).
-    waves_of_n = {int(n): int(wv) for n, _, wv in mixed["mapping"]}
+    waves_of_n = {int(m[0]): int(m[2]) for m in mixed["mapping"]}
     occupied = min(1024, sum(int(r) * waves_of_n[int(n)] for n, r in zip(w.n_beads, w.n_slots)))
     fp64_sweep_s = fp64["sweep_kernel_ms"] / 1e3 / args.steps
 

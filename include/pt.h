@@ -74,7 +74,8 @@ enum pt_status {
     PT_ENOMEM = -3,        /* workspace smaller than pt_workspace_bytes()        */
     PT_EHIP = -4,          /* a HIP runtime call failed                          */
     PT_ESTATE = -5,        /* call not valid in the handle's current state       */
-    PT_EUNSUPPORTED = -6   /* chain longer than the kernels support (N > 2048)   */
+    PT_EUNSUPPORTED = -6   /* chain longer than the kernels support (N > 2048), or
+                              PT_MAP_LANE with PT_MIXED                          */
 };
 
 enum pt_precision { PT_FP64 = 0, PT_MIXED = 1 };
@@ -107,11 +108,13 @@ typedef struct pt_config {
     int64_t log_capacity;           /* sweeps of accept bits and exchange outcomes kept
                                        on the device; 0 = none                         */
     int32_t schedule;               /* PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or
-                                       PT_SCHED_PERSISTENT (same results)              */
+                                       PT_SCHED_PERSISTENT (same results), optionally
+                                       | PT_SCHED_FULL_ENERGY                          */
     const int32_t *mapping;         /* [n_chains] 16*B + W (beads per lane B in
                                        {1,2,4,8}, wavefronts per replica W in {1,2,4},
-                                       64*W*B >= N) or 0 for the default; NULL = all
-                                       default.  Results do not depend on it.          */
+                                       64*W*B >= N), optionally | PT_MAP_LANE, or 0
+                                       for the default; NULL = all default.  Results
+                                       do not depend on it.                            */
 } pt_config;
 
 /* How pt_sweep runs a class of chains (chains with the same mapping).
@@ -121,6 +124,19 @@ typedef struct pt_config {
  * all replicas of the class fit on the device at once (else PER_SWEEP).
  * AUTO = PERSISTENT. */
 enum pt_schedule { PT_SCHED_AUTO = 0, PT_SCHED_PER_SWEEP = 1, PT_SCHED_PERSISTENT = 2 };
+
+/* The paper's alternative designs, kept as measured alternatives (Sec. 3.4,
+ * Sec. 4.2); results are unchanged bit for bit.
+ * PT_SCHED_FULL_ENERGY (or-ed into config.schedule): every sweep ends with
+ * the FP64-order energy E(C) of Eq. (4), recomputed from scratch, in place
+ * of the running sum of the accepted moves' differences (which is otherwise
+ * replaced only when its error bound has grown); the recorded E is then the
+ * FP64-order energy of every sweep.
+ * PT_MAP_LANE (or-ed into a chain's mapping code, precision PT_FP64 only):
+ * one lane runs the whole sweep of one replica, 64 replicas per wavefront,
+ * coordinates read from and written to device memory bead by bead (the
+ * 16*B + W part then only fixes the storage layout); never persistent. */
+enum pt_ablation { PT_SCHED_FULL_ENERGY = 16, PT_MAP_LANE = 0x100 };
 
 typedef struct pt_handle pt_handle;
 
@@ -184,11 +200,12 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
                        uint8_t *h_exch_log, int64_t *exch_rows);
 
 /* Autotuner of the mapping.  For every distinct chain length of the batch it
- * times each mapping with 64 W B in [N, max(64, 4N)) on the batch's chains of
- * that length (their own slots, ladders, coordinates, precision and
- * schedule) over trial_sweeps sweeps after a warm-up, in a device workspace of
- * its own on hip_stream, and writes the fastest as 16 B + W to
- * mapping_out[n_chains] (ready for config.mapping).  Unless the schedule is
+ * times each mapping with 64 W B in [N, max(64, 4N)) -- and, for PT_FP64, one
+ * lane per replica (PT_MAP_LANE) -- on the batch's chains of that length
+ * (their own slots, ladders, coordinates, precision and schedule) over
+ * trial_sweeps sweeps after a warm-up, in a device workspace of its own on
+ * hip_stream, and writes the fastest code to mapping_out[n_chains] (ready for
+ * config.mapping).  Unless the schedule is
  * PT_SCHED_PER_SWEEP it then merges classes greedily -- all chains of one
  * mapping moved to a wider one that holds them -- while the whole batch,
  * timed the same way, gets at least 2% faster and every class still runs

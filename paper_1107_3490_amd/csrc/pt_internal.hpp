@@ -66,6 +66,7 @@ struct Tables {
     int32_t total_slots;
     int32_t exchange_every;
     uint32_t spin_limit;         // polls of a persistent run's partner wait before it gives up
+    int32_t full_energy;         // nonzero: every sweep ends with the FP64-order energy
     uint64_t seed;
     Consts k;
 };
@@ -75,6 +76,9 @@ struct Tables {
 // slots (energy) or chains (exchange) of that class.
 hipError_t launch_sweep(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *slot_list,
                         int n_items, hipStream_t s);
+// One lane per replica (FP64 order): same results as launch_sweep.
+hipError_t launch_sweep_lane(int bpl, int wpr, const Tables &T, const int32_t *slot_list, int n_items,
+                             hipStream_t s);
 hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *conf_list, int n_items,
                          double *out_e, double *out_b, hipStream_t s);
 hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *chain_list, int n_chains,

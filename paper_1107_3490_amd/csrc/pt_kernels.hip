@@ -78,9 +78,9 @@ __device__ __forceinline__ double bound_energy(const Consts &k, int log_np, int 
 // as a binary counter: stk[l] holds the pending left sibling of size 2^l.
 // idx is uniform across the wavefront; after leaf 2^L - 1 the complete tree
 // over 2^L leaves sits in stk[L].
-template <int LEVELS>
-__device__ __forceinline__ void tree_push(double (&stk)[LEVELS + 1], int idx, double v) {
-    double carry = v;
+template <int LEVELS, class V>
+__device__ __forceinline__ void tree_push(V (&stk)[LEVELS + 1], int idx, V v) {
+    V carry = v;
     bool placed = false;
 #pragma unroll
     for (int l = 0; l <= LEVELS; ++l) {
@@ -482,7 +482,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
 // (Eq. 8) into the accumulators and the series; the running energy of
 // conformation q.  The running energy is first replaced by the FP64-order
 // energy when its bound has grown past resync_rel of max(1, |E|) (a start
-// with near-overlapping beads, or many accepted moves).  Wavefront 0 does the
+// with near-overlapping beads, or many accepted moves), or after every sweep
+// when the run recomputes the full energy each sweep.  Wavefront 0 does the
 // work; E and Bd leave valid in every thread.
 template <int B, int W>
 __device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S, int g, int q,
@@ -496,7 +497,7 @@ __device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S,
         double ree2, rg2;
         shape_wave<B, W>(X, Y, Z, n, ree2, rg2);
         bool resync = false;
-        if (!(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
+        if (T.full_energy || !(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
             E = energy_wave<B, W>(X, Y, Z, n, K);
             Bd = bound_energy(K, log2c(n), n, E, 0.0);
             resync = true;
@@ -568,6 +569,198 @@ __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_sweep(const T
     sweep_moves<B, W, MIXED>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
     copy_replica<B, W, G::NT>(cq, S.xyz);
     sweep_record<B, W>(T, S, g, q, n, t64, E, Bd, n_acc, n_rescore);
+}
+
+// --------------------------------------------------- one lane per replica --
+// The paper's first GPU design (Sec. 4.2: one thread runs the whole sweep of
+// a replica), kept as a measured alternative mapping.  Here 64 replicas share
+// a wavefront, one per lane, and each lane reads and writes its replica in
+// HBM, bead by bead, in the (B, W) layout of its class.  Every sum is the
+// pairwise tree of the wavefront kernels taken serially, so decisions,
+// coordinates, energies and bounds equal theirs bit for bit.  FP64 order only.
+
+// Pairwise tree over leaf(0) .. leaf(n - 1) padded with zeros to a power of
+// two, in one thread: static trees over aligned chunks of 16 leaves chained
+// by a binary counter (leaf(j) must be an exact zero for j >= n).  The pending
+// subtrees left in the counter are the blocks of the binary expansion of the
+// chunk count; adding them from the right gives the tree over the next power
+// of two, whose remaining leaves are zeros.
+template <int NP, class V, class F>
+__device__ __forceinline__ V serial_tree(int n, const F &leaf) {
+    constexpr int LV = ilog2(NP / 16);
+    V stk[LV + 1];
+    const int nc = (n + 15) >> 4;
+    for (int c = 0; c < nc; ++c) {
+        const V v = lane_tree<0, 16>([&](int b) { return leaf(c * 16 + b); });
+        tree_push<LV>(stk, c, v);
+    }
+    V acc{};
+    bool have = false;
+#pragma unroll
+    for (int l = 0; l <= LV; ++l) {
+        if ((nc >> l) & 1) {
+            acc = have ? stk[l] + acc : stk[l];
+            have = true;
+        }
+    }
+    return acc;
+}
+
+// Ree^2, Rg^2 (Eq. 8) and the FP64-order energy (Eq. 4) of a replica in the
+// (B, W) layout, in one thread: the trees of shape_wave and energy_wave.
+template <int B, int W>
+__device__ void shape_serial(const double *X, const double *Y, const double *Z, int n,
+                             double &ree2, double &rg2) {
+    using G = Geo<B, W>;
+    const int a0 = G::pos(0), a1 = G::pos(n - 1);
+    ree2 = sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]);
+    auto mean = [&](const double *C) {
+        return serial_tree<G::NP, double>(n, [&](int j) { return (j < n) ? C[G::pos(j)] : 0.0; }) /
+               (double)n;
+    };
+    const double mx = mean(X), my = mean(Y), mz = mean(Z);
+    rg2 = serial_tree<G::NP, double>(n, [&](int j) {
+              if (j >= n) return 0.0;
+              const int a = G::pos(j);
+              return sq3(X[a] - mx, Y[a] - my, Z[a] - mz);
+          }) /
+          (double)n;
+}
+
+template <int B, int W>
+__device__ double energy_serial(const double *X, const double *Y, const double *Z, int n,
+                                const Consts &k) {
+    using G = Geo<B, W>;
+    constexpr int LN = G::LOG_NP;
+    double rows[LN + 1];
+    for (int i = 0; i < n; ++i) {
+        const int ai = G::pos(i);
+        const double xi = X[ai], yi = Y[ai], zi = Z[ai];
+        const double row = serial_tree<G::NP, double>(n, [&](int j) {
+            if (!(j > i && j < n)) return 0.0;
+            const int a = G::pos(j);
+            return lj64(k, sq3(X[a] - xi, Y[a] - yi, Z[a] - zi));
+        });
+        tree_push<LN>(rows, i, row);
+    }
+    double e_lj = 0.0;
+    bool have = false;
+#pragma unroll
+    for (int l = 0; l <= LN; ++l) {
+        if ((n >> l) & 1) {
+            e_lj = have ? rows[l] + e_lj : rows[l];
+            have = true;
+        }
+    }
+    const double e_fene = serial_tree<G::NP, double>(n, [&](int i) {
+        if (i >= n - 1) return 0.0;
+        const int a0 = G::pos(i), a1 = G::pos(i + 1);
+        return fene64(k, sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]));
+    });
+    return e_lj + e_fene;
+}
+
+// One sweep and its record for each slot in `list`, one lane per slot.
+template <int B, int W>
+__global__ __launch_bounds__(64) void k_sweep_lane(const Tables T, const int32_t *__restrict__ list,
+                                                   int n_items) {
+    using G = Geo<B, W>;
+    const int idx = blockIdx.x * 64 + threadIdx.x;
+    if (idx >= n_items) return;  // no barriers below
+    const int g = list[idx];
+    const int n = T.chain_n[T.slot_chain[g]];
+    const int64_t t64 = T.te[0];
+    const uint32_t t = (uint32_t)t64;
+    const int q = T.perm[g];
+    double *const X = T.coords + T.coord_off[q];
+    double *const Y = X + G::NP, *const Z = X + 2 * G::NP;
+    const Consts &K = T.k;
+    const double beta = T.beta[g];
+    const uint32_t gid = T.slot_gid[g];
+    uint64_t *logrow = (T.accept_log != nullptr && t64 < T.log_cap)
+                           ? T.accept_log + t64 * T.words_total + T.word_off[g]
+                           : nullptr;
+    uint64_t word = 0, digest = T.dig[2 * g];
+    double E = T.e_run[q], Bd = T.b_run[q];
+    int64_t n_acc = 0;
+    const int lg = log2c(n);
+    for (int m = 0; m < n; ++m) {
+        // Draws of move m (Philox counters (m, t, g, 0) and (m, t, g, 1)).
+        const U4 w = philox10(U4{(uint32_t)m, t, gid, 0u}, T.seed);
+        const U4 v = philox10(U4{(uint32_t)m, t, gid, 1u}, T.seed);
+        const int k = (int)(((uint64_t)w.x * (uint64_t)(uint32_t)n) >> 32);
+        const double th = -det_log(unit_open(v.x));
+        const int ak = G::pos(k);
+        const double xo = X[ak], yo = Y[ak], zo = Z[ak];
+        const double xn = xo + (unit_open(w.y) - 0.5) * K.edge;
+        const double yn = yo + (unit_open(w.z) - 0.5) * K.edge;
+        const double zn = zo + (unit_open(w.w) - 0.5) * K.edge;
+        // Bond differences (Eq. 3), a missing neighbour giving 0.
+        double dfl = 0.0, dfr = 0.0;
+        if (k > 0) {
+            const int a = G::pos(k - 1);
+            const double xl = X[a], yl = Y[a], zl = Z[a];
+            dfl = fene64(K, sq3(xl - xn, yl - yn, zl - zn)) - fene64(K, sq3(xl - xo, yl - yo, zl - zo));
+        }
+        if (k + 1 < n) {
+            const int a = G::pos(k + 1);
+            const double xr = X[a], yr = Y[a], zr = Z[a];
+            dfr = fene64(K, sq3(xr - xn, yr - yn, zr - zn)) - fene64(K, sq3(xr - xo, yr - yo, zr - zo));
+        }
+        // Pair sum (Eqs. 1, 4): the moved bead's own leaf and j >= n are zeros.
+        const Leaf64 s = serial_tree<G::NP, Leaf64>(n, [&](int j) {
+            if (j == k || j >= n) return Leaf64{0.0, 0.0};
+            const int a = G::pos(j);
+            const double en = lj64(K, sq3(X[a] - xn, Y[a] - yn, Z[a] - zn));
+            const double eo = lj64(K, sq3(X[a] - xo, Y[a] - yo, Z[a] - zo));
+            const double tt = en - eo;
+            return Leaf64{tt, dabs(tt)};
+        });
+        const double de = s.t + (dfl + dfr);
+        // Metropolis (Eq. 5) in the log domain.
+        if ((de <= 0.0) || (beta * de < th)) {
+            X[ak] = xn;
+            Y[ak] = yn;
+            Z[ak] = zn;
+            E = E + de;
+            Bd = Bd + bound64(lg, s.a, dfl, dfr, de) + 0x1p-52 * dabs(E);
+            ++n_acc;
+            word |= 1ull << (m & 63);
+        }
+        if ((m & 63) == 63 || m == n - 1) {
+            if (logrow != nullptr) logrow[m >> 6] = word;
+            digest = mix64(digest ^ word);
+            word = 0;
+        }
+    }
+    T.dig[2 * g] = digest;
+    // Record, as sweep_record.
+    double ree2, rg2;
+    shape_serial<B, W>(X, Y, Z, n, ree2, rg2);
+    bool resync = false;
+    if (T.full_energy || !(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
+        E = energy_serial<B, W>(X, Y, Z, n, K);
+        Bd = bound_energy(K, lg, n, E, 0.0);
+        resync = true;
+    }
+    T.e_run[q] = E;
+    T.b_run[q] = Bd;
+    int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
+    cnt[0] += n_acc;
+    cnt[5] += n;
+    cnt[6] += resync ? 1 : 0;
+    double *ac = T.acc + (int64_t)g * 5;
+    ac[0] += 1.0;
+    ac[1] += E;
+    ac[2] += E * E;
+    ac[3] += rg2;
+    ac[4] += ree2;
+    if (T.series != nullptr && t64 < T.series_cap) {
+        double *row = T.series + (t64 * T.total_slots + g) * 3;
+        row[0] = E;
+        row[1] = ree2;
+        row[2] = rg2;
+    }
 }
 
 // ----------------------------------------------------------------- energy --
@@ -902,6 +1095,12 @@ hipError_t sweep_bw(bool mixed, const Tables &T, const int32_t *list, int n, hip
 }
 
 template <int B, int W>
+hipError_t sweep_lane_bw(const Tables &T, const int32_t *list, int n, hipStream_t s) {
+    hipLaunchKernelGGL((k_sweep_lane<B, W>), dim3((n + 63) / 64), dim3(64), 0, s, T, list, n);
+    return hipGetLastError();
+}
+
+template <int B, int W>
 hipError_t energy_bw(const Tables &T, const int32_t *list, int n, double *oe, double *ob, int by_slot,
                      hipStream_t s) {
     hipLaunchKernelGGL((k_energy<B, W>), dim3(n), dim3(64), 0, s, T, list, oe, ob, by_slot);
@@ -958,6 +1157,13 @@ hipError_t launch_sweep(int bpl, int wpr, bool mixed, const Tables &T, const int
 #define PT_SW(B, W) sweep_bw<B, W>(mixed, T, list, n, s)
     PT_DISPATCH(bpl, wpr, PT_SW)
 #undef PT_SW
+}
+
+hipError_t launch_sweep_lane(int bpl, int wpr, const Tables &T, const int32_t *list, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+#define PT_SL(B, W) sweep_lane_bw<B, W>(T, list, n, s)
+    PT_DISPATCH(bpl, wpr, PT_SL)
+#undef PT_SL
 }
 
 hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *list, int n, double *out_e,

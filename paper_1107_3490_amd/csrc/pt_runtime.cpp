@@ -13,6 +13,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pt.h"
@@ -62,6 +63,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     int n_chains = 0, total = 0;
     std::vector<int> bpl, wpr;        // per chain
+    std::vector<char> lane;           // per chain: one lane per replica
     std::vector<int64_t> coord_off;   // per conformation (doubles)
     std::vector<int64_t> word_off;    // per slot
     int64_t coord_total = 0, words_total = 0;
@@ -87,16 +89,21 @@ int validate(const pt_model *m, const pt_config *c) {
     if (c->precision != PT_FP64 && c->precision != PT_MIXED) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_MIXED");
     if (c->exchange_every < 0) return fail(PT_EINVAL, "exchange_every must be >= 0");
     if (c->series_capacity < 0 || c->log_capacity < 0) return fail(PT_EINVAL, "capacities must be >= 0");
-    if (c->schedule < PT_SCHED_AUTO || c->schedule > PT_SCHED_PERSISTENT)
-        return fail(PT_EINVAL, "schedule must be PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or PT_SCHED_PERSISTENT");
+    const int sched = c->schedule & ~PT_SCHED_FULL_ENERGY;
+    if (sched < PT_SCHED_AUTO || sched > PT_SCHED_PERSISTENT)
+        return fail(PT_EINVAL, "schedule must be PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or PT_SCHED_PERSISTENT, "
+                               "optionally with PT_SCHED_FULL_ENERGY");
     int64_t total = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
         if (c->n_beads[ch] < 2) return fail(PT_EINVAL, "chain %d: n_beads must be >= 2", ch);
         if (c->mapping != nullptr && c->mapping[ch] != 0) {
-            const int code = c->mapping[ch], B = code >> 4, W = code & 15;
+            const int code = c->mapping[ch], B = (code >> 4) & 15, W = code & 15;
             const bool okb = B == 1 || B == 2 || B == 4 || B == 8, okw = W == 1 || W == 2 || W == 4;
-            if (!okb || !okw || (code & ~0xFF) != 0)
-                return fail(PT_EINVAL, "chain %d: mapping %d is not 16*B + W with B in {1,2,4,8}, W in {1,2,4}", ch, code);
+            if (!okb || !okw || (code & ~(0xFF | PT_MAP_LANE)) != 0)
+                return fail(PT_EINVAL, "chain %d: mapping %d is not 16*B + W with B in {1,2,4,8}, W in {1,2,4} "
+                                       "(optionally + PT_MAP_LANE)", ch, code);
+            if ((code & PT_MAP_LANE) != 0 && c->precision != PT_FP64)
+                return fail(PT_EUNSUPPORTED, "chain %d: mapping PT_MAP_LANE runs the FP64 order only", ch);
             if (64 * W * B < c->n_beads[ch])
                 return fail(PT_EINVAL, "chain %d: mapping B=%d W=%d holds %d < %d beads", ch, B, W, 64 * W * B, c->n_beads[ch]);
         }
@@ -152,13 +159,15 @@ Layout plan(const pt_config *c) {
     L.total = (int)total;
     L.bpl.resize(c->n_chains);
     L.wpr.resize(c->n_chains);
+    L.lane.assign(c->n_chains, 0);
     L.coord_off.resize(total);
     L.word_off.resize(total);
     int g = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
         if (c->mapping != nullptr && c->mapping[ch] != 0) {
-            L.bpl[ch] = c->mapping[ch] >> 4;
+            L.bpl[ch] = (c->mapping[ch] >> 4) & 15;
             L.wpr[ch] = c->mapping[ch] & 15;
+            L.lane[ch] = (c->mapping[ch] & PT_MAP_LANE) != 0;
         } else {
             mapping(c->n_beads[ch], &L.bpl[ch], &L.wpr[ch]);
         }
@@ -220,6 +229,7 @@ double fene_y(const pt::Consts &k, const double *a, const double *b) {
 
 struct Class {
     int bpl = 0, wpr = 0;
+    bool lane = false;        // one lane per replica (FP64 order, per-sweep launches)
     bool persistent = false;  // whole sweeps run by one cooperative launch
     int n_slots = 0, n_chains = 0, max_pairs = 0;
     int32_t *d_slots = nullptr;   // slot (= starting conformation) list
@@ -247,10 +257,15 @@ struct pt_handle {
 
 namespace {
 
+hipError_t launch_class_sweep(const pt_handle *h, const Class &c, hipStream_t s) {
+    if (c.lane) return pt::launch_sweep_lane(c.bpl, c.wpr, h->T, c.d_slots, c.n_slots, s);
+    return pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, s);
+}
+
 int enqueue_sweep(pt_handle *h, hipStream_t s) {
     for (const Class &c : h->classes) {
         if (c.persistent) continue;
-        hipError_t e = pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, s);
+        hipError_t e = launch_class_sweep(h, c, s);
         if (e != hipSuccess) return fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     }
     for (const Class &c : h->classes) {
@@ -390,19 +405,21 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.total_slots = S;
     T.exchange_every = cfg->exchange_every;
     T.spin_limit = 1u << 24;
+    T.full_energy = (cfg->schedule & PT_SCHED_FULL_ENERGY) != 0 ? 1 : 0;
     T.seed = cfg->seed;
     T.k = k;
     h->d_tmp = (double *)(w + L.o_tmp);
 
-    // Classes by (beads per lane, wavefronts per replica).
-    std::map<std::pair<int, int>, std::vector<int>> cls_chains;
-    for (int ch = 0; ch < C; ++ch) cls_chains[{L.bpl[ch], L.wpr[ch]}].push_back(ch);
+    // Classes by (beads per lane, wavefronts per replica, one lane per replica).
+    std::map<std::tuple<int, int, int>, std::vector<int>> cls_chains;
+    for (int ch = 0; ch < C; ++ch) cls_chains[{L.bpl[ch], L.wpr[ch], (int)L.lane[ch]}].push_back(ch);
     std::vector<int32_t> lists;
     lists.reserve(L.lists_len);
     for (auto &kv : cls_chains) {
         Class cl;
-        cl.bpl = kv.first.first;
-        cl.wpr = kv.first.second;
+        cl.bpl = std::get<0>(kv.first);
+        cl.wpr = std::get<1>(kv.first);
+        cl.lane = std::get<2>(kv.first) != 0;
         const size_t slot_at = lists.size();
         for (int ch : kv.second)
             for (int s = 0; s < cfg->n_slots[ch]; ++s) lists.push_back(chain_slot0[ch] + s);
@@ -461,8 +478,9 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "initialisation failed: %s", hipGetErrorString(e)));
     // Persistent schedule for every class whose replicas fit on the device at once.
-    if (cfg->schedule != PT_SCHED_PER_SWEEP) {
+    if ((cfg->schedule & ~PT_SCHED_FULL_ENERGY) != PT_SCHED_PER_SWEEP) {
         for (Class &cl : h->classes) {
+            if (cl.lane) continue;
             int fits = 0;
             e = pt::launch_run(cl.bpl, cl.wpr, h->mixed, T, cl.d_slots, cl.n_slots, 0, 0, 0, &fits, h->stream);
             if (e != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e)));
@@ -562,7 +580,7 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
         for (const Class &c : h->classes) {
             if (c.persistent) continue;
             PT_HIP(hipEventRecord(ev[2 * k], h->stream));
-            hipError_t e = pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, h->stream);
+            hipError_t e = launch_class_sweep(h, c, h->stream);
             if (e != hipSuccess) { rc = fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e)); break; }
             PT_HIP(hipEventRecord(ev[2 * k + 1], h->stream));
             ++k;
@@ -707,7 +725,8 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr, int32_t *per
         if (persistent) {
             persistent[c] = 0;
             for (const Class &cl : h->classes)
-                if (cl.bpl == h->L.bpl[c] && cl.wpr == h->L.wpr[c]) persistent[c] = cl.persistent ? 1 : 0;
+                if (cl.bpl == h->L.bpl[c] && cl.wpr == h->L.wpr[c] && cl.lane == (h->L.lane[c] != 0))
+                    persistent[c] = cl.persistent ? 1 : 0;
         }
     }
     return PT_OK;
@@ -931,6 +950,12 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
                 const int np = 64 * W * B;
                 if (np >= n && np < std::max(65, 4 * n)) cand.push_back(16 * B + W);
             }
+        // The FP64 order can also run one lane per replica (in the default layout).
+        if (cfg->precision == PT_FP64) {
+            int b = 0, w = 0;
+            mapping(n, &b, &w);
+            cand.push_back(PT_MAP_LANE | (16 * b + w));
+        }
         int best = 0;
         if (cand.size() == 1) {
             best = cand[0];
@@ -984,7 +1009,7 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
     // class whose chains finish early only adds its time.  Moving a class into
     // a wider one that runs longer hides it, as long as the merged class still
     // fits on the device at once: greedy merges, timed on the whole batch.
-    if (cfg->schedule != PT_SCHED_PER_SWEEP) {
+    if ((cfg->schedule & ~PT_SCHED_FULL_ENERGY) != PT_SCHED_PER_SWEEP) {
         pt_config t = *cfg;
         t.series_capacity = 0;
         t.log_capacity = 0;
@@ -998,7 +1023,7 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
             pt_handle *h = nullptr;
             int r = pt_init(model, &t, ws, bytes, hip_stream, &h);
             *ok = r == PT_OK;
-            for (int c = 0; r == PT_OK && c < C; ++c) *ok = *ok && h->L.bpl[c] == (m[c] >> 4);
+            for (int c = 0; r == PT_OK && c < C; ++c) *ok = *ok && h->L.bpl[c] == ((m[c] >> 4) & 15);
             if (r == PT_OK)
                 for (const Class &cl : h->classes) *ok = *ok && cl.persistent;
             if (r == PT_OK) r = pt_sweep(h, std::min<int64_t>(trial_sweeps, 4));
@@ -1020,7 +1045,9 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
             for (auto &x : max_n)
                 for (auto &y : max_n) {
                     const int cy = y.first;
-                    if (x.first == cy || 64 * (cy & 15) * (cy >> 4) < x.second) continue;
+                    if (x.first == cy || ((x.first | cy) & PT_MAP_LANE) != 0 ||
+                        64 * (cy & 15) * ((cy >> 4) & 15) < x.second)
+                        continue;
                     std::vector<int32_t> cand = mp;
                     for (int c = 0; c < C; ++c)
                         if (cand[c] == x.first) cand[c] = cy;

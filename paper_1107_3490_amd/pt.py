@@ -24,6 +24,10 @@ LIB_PATH = os.path.join(HERE, "libpt.so")
 PT_OK, PT_EINVAL, PT_EDOMAIN, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PT_FP64, PT_MIXED = 0, 1
 PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT = 0, 1, 2
+# The paper's alternative designs (see include/pt.h): or-ed into the schedule
+# (full energy after every sweep) or into a chain's mapping code (one lane per
+# replica, FP64 only).
+PT_SCHED_FULL_ENERGY, PT_MAP_LANE = 16, 0x100
 
 # Diagnostic ops of pt_selftest.
 OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32 = range(9)
@@ -227,7 +231,8 @@ def pt_destroy(h: int) -> None:
 
 def autotune(w, precision: Optional[str] = None, schedule: int = PT_SCHED_AUTO,
              trial_sweeps: int = 20) -> np.ndarray:
-    """pt_autotune on workload w: one mapping code (16 B + W) per chain."""
+    """pt_autotune on workload w: one mapping code (16 B + W, possibly
+    | PT_MAP_LANE for FP64) per chain."""
     import torch
 
     prec = precision or w.precision

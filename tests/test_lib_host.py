@@ -114,7 +114,8 @@ def test_mapping_override_is_validated(L):
     base = pt.pt_workspace_bytes(m, cfg)
     assert base > 0
     for code, ok in ((0x21, True), (0x12, True), (0x14, True), (0x84, True), (0x11, False),
-                     (0x31, False), (0x23, False), (0x121, False), (-1, False)):
+                     (0x31, False), (0x23, False), (0x121, True), (0x111, False), (0x221, False),
+                     (-1, False)):
         mp = np.array([code], dtype=np.int32)
         cfg.mapping = pt._ptr(mp, C.c_int32)
         n = L.pt_workspace_bytes(C.byref(m), C.byref(cfg))
@@ -125,3 +126,26 @@ def test_mapping_override_is_validated(L):
     mp = np.array([0x84], dtype=np.int32)
     cfg.mapping = pt._ptr(mp, C.c_int32)
     assert L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) > base
+
+
+def test_ablation_flags_are_validated(L):
+    """One lane per replica runs the FP64 order only; the full-energy flag is
+    the only flag the schedule takes."""
+    m = pt.model_struct(I.model_params())
+    w = I.make_workload([100], [2], [(0.1, 1.5)], "straight", 1, 0, "fp64")
+    cfg, keep = _cfg(w, precision=pt.PT_MIXED)
+    mp = np.array([pt.PT_MAP_LANE | 0x21], dtype=np.int32)
+    cfg.mapping = pt._ptr(mp, C.c_int32)
+    assert L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) == 0
+    assert "PT_MAP_LANE" in L.pt_last_error().decode()
+    cfg.precision = pt.PT_FP64
+    assert L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) > 0
+    cfg.mapping = None
+    for sched, ok in ((pt.PT_SCHED_FULL_ENERGY, True), (pt.PT_SCHED_PER_SWEEP | pt.PT_SCHED_FULL_ENERGY, True),
+                      (pt.PT_SCHED_PERSISTENT | pt.PT_SCHED_FULL_ENERGY, True), (3, False), (32, False),
+                      (pt.PT_SCHED_FULL_ENERGY | 3, False), (-1, False)):
+        cfg.schedule = sched
+        n = L.pt_workspace_bytes(C.byref(m), C.byref(cfg))
+        assert (n > 0) == ok, (sched, n)
+        if not ok:
+            assert "schedule" in L.pt_last_error().decode()
