@@ -188,7 +188,9 @@ def ablations(sweeps=40, warmup=5):
         N = 55 chain as a function of the number of replicas;
       * the full FP64-order energy recomputed after every sweep (the paper's
         per-sweep energy) against the running energy, on the N = 100 and
-        N = 500 workloads and the N = 55 chain at 4096 replicas."""
+        N = 500 workloads and the N = 55 chain at 4096 replicas;
+      * the paper's one-pair-per-thread energy kernel against the FP64-order
+        one (one wavefront per conformation, a row per lane)."""
     import torch
     from paper_1107_3490_amd import inputs as I
     from paper_1107_3490_amd import pt
@@ -224,9 +226,30 @@ def ablations(sweeps=40, warmup=5):
                                 "running_energy_ms_per_sweep": run_ms,
                                 "full_energy_ms_per_sweep": full_ms,
                                 "full_over_running": full_ms / run_ms})
-    return {"ablations": "paper's alternative designs vs this library's, one MI355X, identical results",
+    method_rows = []
+    for name, w in (("c2", I.named("c2")), ("c3", I.named("c3")), ("N=55 x 4096", chain55(4096)),
+                    ("c5 chain 0 (N=2000 x 256)", I.subset(I.named("c5"), [0]))):
+        s = pt.Simulation(w, precision="fp64")
+        row = {"workload": name}
+        for key, method in (("fp64_order", pt.PT_ENERGY_FP64_ORDER),
+                            ("pair_per_thread", pt.PT_ENERGY_PAIR_PER_THREAD)):
+            times = []
+            for _ in range(3):
+                e, b, ms = s.energy_method(method)
+                times.append(ms)
+            row[key + "_ms"] = min(times)
+            row[key + "_max_bound"] = float(np.max(b))
+        exact = s.energy()
+        row["pair_per_thread_max_abs_diff"] = float(np.max(np.abs(e - exact)))
+        row["pair_energies_per_s_fp64_order"] = 0.5 * sum(
+            r * n * (n - 1) for n, r in zip(w.n_beads, w.n_slots)) / (row["fp64_order_ms"] / 1e3)
+        row["pair_over_fp64_order_time"] = row["pair_per_thread_ms"] / row["fp64_order_ms"]
+        s.close()
+        method_rows.append(row)
+    return {"ablations": "paper's alternative designs vs this library's, one MI355X, identical results "
+                         "(the pair-per-thread energy: within its rigorous bound)",
             "sweeps": sweeps, "one_lane_per_replica_fp64_N55_edge0.02": lane_rows,
-            "full_energy_every_sweep": energy_rows}
+            "full_energy_every_sweep": energy_rows, "energy_kernels": method_rows}
 
 
 def main():

@@ -165,6 +165,23 @@ PT_API int pt_exchange(pt_handle *h);
  * each slot, [sum R_c] doubles, chain-major. */
 PT_API int pt_energy(pt_handle *h, double *h_energy);
 
+/* Energy of each slot's conformation (Eq. 4) by one of two methods,
+ * synchronous, [sum R_c] doubles each:
+ *   PT_ENERGY_FP64_ORDER: the FP64-order energy of pt_energy (one wavefront
+ *     per conformation, one row of pairs per lane); h_bound gets the a-priori
+ *     bound on |E - exact sum of the FP64 terms| that the kernels use;
+ *   PT_ENERGY_PAIR_PER_THREAD: the paper's parallel energy (Sec. 3.4): the
+ *     coordinates in LDS, every thread sums one pair per round, rows i and
+ *     N-2-i sharing a round, then a reduction over threads; for even N the
+ *     middle round takes its row once (the printed enumeration skips it).
+ *     Not the FP64 order: E differs from it by rounding, and h_bound gets a
+ *     rigorous bound on |E - exact sum of the same FP64 terms|.
+ * h_bound and kernel_ms (HIP event time of the energy launches on the
+ * handle's stream, ms) may be NULL.  Errors: PT_EINVAL, PT_EHIP. */
+enum pt_energy_method { PT_ENERGY_FP64_ORDER = 0, PT_ENERGY_PAIR_PER_THREAD = 1 };
+PT_API int pt_energy_method(pt_handle *h, int32_t method, double *h_energy, double *h_bound,
+                            double *kernel_ms);
+
 /* Observables and counters.  Every pointer may be NULL.  Synchronous.
  *   acc     [slots][5]: sweeps recorded, sum E, sum E^2, sum Rg^2, sum Ree^2
  *           (E is the running energy; Rg^2 per Eq. 8; Ree^2 = |r_N - r_1|^2)

@@ -81,6 +81,10 @@ hipError_t launch_sweep_lane(int bpl, int wpr, const Tables &T, const int32_t *s
                              hipStream_t s);
 hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *conf_list, int n_items,
                          double *out_e, double *out_b, hipStream_t s);
+// The paper's one-pair-per-thread energy of each slot's conformation (not the
+// FP64 order), with a rigorous error bound; out_e / out_b indexed by slot.
+hipError_t launch_energy_pairs(int bpl, int wpr, const Tables &T, const int32_t *slot_list, int n_items,
+                               double *out_e, double *out_b, hipStream_t s);
 hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *chain_list, int n_chains,
                            int max_pairs, int force, hipStream_t s);
 hipError_t launch_advance(const Tables &T, int force, hipStream_t s);

@@ -785,6 +785,78 @@ __global__ __launch_bounds__(64) void k_energy(const Tables T, const int32_t *__
     }
 }
 
+// Energy E(C) of Eq. (4) the way of the paper's energy routine (Sec. 3.4):
+// the coordinates in LDS, one pair per thread per round.  With N virtual
+// threads v (thread tid of the block takes v = tid B + b, b < B), v first
+// takes its bond (v, v+1), then in round i = 0 .. floor(N/2) - 1 the pair
+// (i, v) when v > i, else (N-2-i, N-1-i+v); rows i and N-2-i together hold
+// N pairs.  For even N the last round has i = N-2-i, where the second form
+// would repeat the first one's pairs: there only v > i take a pair (the
+// printed enumeration drops that whole round instead, and with it row i).
+// Each v sums its terms in order; the N sums meet in the pairwise tree over v.
+// Not the FP64 order: out_b[g] receives a rigorous bound on |E - exact sum of
+// the same FP64 terms|, (m + log2 NP + 3) 2^-52 sum |terms| with m = floor(N/2)
+// + 1 terms per v (recursive sums, then the tree, with a factor-two margin);
+// out_e, out_b are indexed by slot.
+template <int B, int W>
+__global__ __launch_bounds__(64 * W) void k_energy_pairs(const Tables T, const int32_t *__restrict__ list,
+                                                        double *out_e, double *out_b) {
+    using G = Geo<B, W>;
+    __shared__ double XYZ[3 * G::NP];
+    __shared__ double part[2][W];
+    double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = list[blockIdx.x];
+    const int q = T.perm[g];
+    const int n = T.chain_n[T.slot_chain[g]];
+    const Consts &K = T.k;
+    copy_replica<B, W, G::NT>(XYZ, T.coords + T.coord_off[q]);
+    __syncthreads();
+    double acc[B], ab[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int v = tid * B + b;
+        acc[b] = 0.0;
+        if (v < n - 1) {
+            const int a0 = G::pos(v), a1 = G::pos(v + 1);
+            acc[b] = fene64(K, sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]));
+        }
+        ab[b] = dabs(acc[b]);
+    }
+    const int rounds = n / 2;
+    for (int i = 0; i < rounds; ++i) {
+        const bool last_even = (n - 2 - i == i);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int v = tid * B + b;
+            const bool upper = v > i;
+            const int i1 = upper ? i : n - 2 - i;
+            const int i2 = upper ? v : n - 1 - i + v;
+            if (v < n && (upper || !last_even)) {
+                const int a1 = G::pos(i1), a2 = G::pos(i2);
+                const double e = lj64(K, sq3(X[a2] - X[a1], Y[a2] - Y[a1], Z[a2] - Z[a1]));
+                acc[b] = acc[b] + e;
+                ab[b] = ab[b] + dabs(e);
+            }
+        }
+    }
+    const Leaf64 s = lane_tree<0, B>([&](int b) { return Leaf64{acc[b], ab[b]}; });
+    double e = wave_tree(s.t), a = wave_tree(s.a);
+    if constexpr (W > 1) {
+        if (lane == 0) {
+            part[0][wv] = e;
+            part[1][wv] = a;
+        }
+        __syncthreads();
+        e = tree_w<W>(part[0]);
+        a = tree_w<W>(part[1]);
+    }
+    if (tid == 0) {
+        out_e[g] = e;
+        out_b[g] = 0x1p-52 * (double)(rounds + 1 + G::LOG_NP + 3) * a;
+    }
+}
+
 // --------------------------------------------------------------- exchange --
 // Decision of one exchange attempt (Sec. 3.3, Eq. 6) between slots (g, g+1)
 // of chain c at exchange step e, holding conformations q1, q2 with running
@@ -1108,6 +1180,12 @@ hipError_t energy_bw(const Tables &T, const int32_t *list, int n, double *oe, do
 }
 
 template <int B, int W>
+hipError_t energy_pairs_bw(const Tables &T, const int32_t *list, int n, double *oe, double *ob, hipStream_t s) {
+    hipLaunchKernelGGL((k_energy_pairs<B, W>), dim3(n), dim3(64 * W), 0, s, T, list, oe, ob);
+    return hipGetLastError();
+}
+
+template <int B, int W>
 hipError_t exchange_bw(const Tables &T, const int32_t *list, int nc, int mp, int force, hipStream_t s) {
     hipLaunchKernelGGL((k_exchange<B, W>), dim3(nc * mp), dim3(64), 0, s, T, list, mp, force);
     return hipGetLastError();
@@ -1173,6 +1251,14 @@ hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *list,
 #define PT_EN(B, W) energy_bw<B, W>(T, list, n, out_e, out_b, by_slot, s)
     PT_DISPATCH(bpl, wpr, PT_EN)
 #undef PT_EN
+}
+
+hipError_t launch_energy_pairs(int bpl, int wpr, const Tables &T, const int32_t *list, int n, double *out_e,
+                               double *out_b, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+#define PT_EP(B, W) energy_pairs_bw<B, W>(T, list, n, out_e, out_b, s)
+    PT_DISPATCH(bpl, wpr, PT_EP)
+#undef PT_EP
 }
 
 hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *list, int n_chains,

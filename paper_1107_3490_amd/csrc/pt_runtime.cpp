@@ -208,7 +208,7 @@ Layout plan(const pt_config *c) {
     L.o_te = take(16);
     L.o_dig = take(16 * S);
     L.o_lists = take(4 * (size_t)L.lists_len);
-    L.o_tmp = take(8 * S);
+    L.o_tmp = take(16 * S);
     L.o_alog = take(8 * (size_t)L.words_total * (size_t)L.log_cap);
     L.o_elog = take(S * (size_t)L.log_cap);
     L.o_series = take(8 * 3 * S * (size_t)L.series_cap);
@@ -641,6 +641,52 @@ PT_API int pt_energy(pt_handle *h, double *h_e) {
     }
     PT_HIP(hipMemcpyAsync(h_e, h->d_tmp, 8 * (size_t)h->L.total, hipMemcpyDeviceToHost, h->stream));
     PT_HIP(hipStreamSynchronize(h->stream));
+    return check_err(h);
+}
+
+PT_API int pt_energy_method(pt_handle *h, int32_t method, double *h_e, double *h_b, double *kernel_ms) {
+    if (h == nullptr || h_e == nullptr) return fail(PT_EINVAL, "NULL argument");
+    if (method != PT_ENERGY_FP64_ORDER && method != PT_ENERGY_PAIR_PER_THREAD)
+        return fail(PT_EINVAL, "unknown energy method %d", method);
+    const size_t S = (size_t)h->L.total;
+    double *d_e = h->d_tmp, *d_b = h->d_tmp + S;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    PT_HIP(hipEventCreate(&ev[0]));
+    PT_HIP(hipEventCreate(&ev[1]));
+    int rc = PT_OK;
+    PT_HIP(hipEventRecord(ev[0], h->stream));
+    for (const Class &c : h->classes) {
+        hipError_t e = method == PT_ENERGY_FP64_ORDER
+                           ? pt::launch_energy(c.bpl, c.wpr, h->T, c.d_slots, c.n_slots, d_e, nullptr, h->stream)
+                           : pt::launch_energy_pairs(c.bpl, c.wpr, h->T, c.d_slots, c.n_slots, d_e, d_b, h->stream);
+        if (e != hipSuccess) {
+            rc = fail(PT_EHIP, "energy launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+    }
+    PT_HIP(hipEventRecord(ev[1], h->stream));
+    if (rc == PT_OK) {
+        PT_HIP(hipMemcpyAsync(h_e, d_e, 8 * S, hipMemcpyDeviceToHost, h->stream));
+        if (h_b && method == PT_ENERGY_PAIR_PER_THREAD)
+            PT_HIP(hipMemcpyAsync(h_b, d_b, 8 * S, hipMemcpyDeviceToHost, h->stream));
+        PT_HIP(hipStreamSynchronize(h->stream));
+        float ms = 0.f;
+        PT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        if (kernel_ms) *kernel_ms = ms;
+        if (h_b && method == PT_ENERGY_FP64_ORDER) {
+            // The a-priori bound of the FP64 order, as the kernels compute it.
+            for (int c = 0, g = 0; c < h->L.n_chains; ++c) {
+                const int n = h->n_beads[c];
+                const int lg = 32 - __builtin_clz((unsigned)(n - 1));
+                const double pairs = 0.5 * (double)n * (double)(n - 1);
+                for (int s = 0; s < h->n_slots[c]; ++s, ++g)
+                    h_b[g] = 0x1p-51 * (double)(2 * lg + 4) * (fabs(h_e[g]) + 2.0 * pairs * h->k.neg_floor);
+            }
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc != PT_OK) return rc;
     return check_err(h);
 }
 

@@ -28,11 +28,13 @@ PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT = 0, 1, 2
 # (full energy after every sweep) or into a chain's mapping code (one lane per
 # replica, FP64 only).
 PT_SCHED_FULL_ENERGY, PT_MAP_LANE = 16, 0x100
+PT_ENERGY_FP64_ORDER, PT_ENERGY_PAIR_PER_THREAD = 0, 1
 
 # Diagnostic ops of pt_selftest.
 OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32 = range(9)
 
 EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_autotune", "pt_sweep", "pt_exchange", "pt_energy",
+           "pt_energy_method",
            "pt_observables", "pt_reset_observables", "pt_get_coords", "pt_get_running",
            "pt_get_series", "pt_get_logs", "pt_get_digests", "pt_state_bytes", "pt_get_state",
            "pt_set_state", "pt_set_spin_limit", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
@@ -141,6 +143,13 @@ def pt_exchange(h: int) -> None:
 
 def pt_energy(h: int, out: np.ndarray) -> None:
     _check(lib().pt_energy(C.c_void_p(h), _ptr(out, C.c_double)))
+
+
+def pt_energy_method(h: int, method: int, out: np.ndarray, bound: np.ndarray) -> float:
+    ms = C.c_double(0.0)
+    _check(lib().pt_energy_method(C.c_void_p(h), int(method), _ptr(out, C.c_double),
+                                  _ptr(bound, C.c_double), C.byref(ms)))
+    return ms.value
 
 
 def pt_observables(h: int, acc, counts, perm, te) -> None:
@@ -322,6 +331,13 @@ class Simulation:
         out = np.zeros(self.total)
         pt_energy(self.h, out)
         return out
+
+    def energy_method(self, method: int):
+        """(energies, error bounds, kernel ms) per slot by PT_ENERGY_FP64_ORDER
+        or PT_ENERGY_PAIR_PER_THREAD."""
+        out, bound = np.zeros(self.total), np.zeros(self.total)
+        ms = pt_energy_method(self.h, method, out, bound)
+        return out, bound, ms
 
     def observables(self) -> dict:
         acc = np.zeros((self.total, 5))

@@ -113,3 +113,28 @@ def test_autotune_considers_one_lane_per_replica_for_fp64():
         b, wv = (c >> 4) & 15, c & 15
         assert b in (1, 2, 4, 8) and wv in (1, 2, 4) and n <= 64 * b * wv
     _assert_same_state(run_gpu(w, 5, "fp64", mapping=codes), run_gpu(w, 5, "fp64"))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 13, 54, 55, 64, 65, 100, 129, 700, 2048])
+def test_pair_per_thread_energy_is_within_its_bound(n):
+    """The paper's one-pair-per-thread energy (even N with the middle round
+    taken once) against the oracle's FP64-order energy: within the sum of the
+    two rigorous bounds, and 1e-12 relative.  A dropped or doubled row (the
+    printed enumeration's even-N round) is many orders above the bound."""
+    pt = _pt()
+    w = I.make_workload([n], [6], [(0.2, 1.5)], "walk", 17 + n, 0, "fp64")
+    s = pt.Simulation(w, precision="fp64")
+    s.sweep(3)
+    e0, b0, _ = s.energy_method(pt.PT_ENERGY_FP64_ORDER)
+    e1, b1, ms = s.energy_method(pt.PT_ENERGY_PAIR_PER_THREAD)
+    exact = s.energy()
+    s.close()
+    orc = O.Simulation(w)
+    orc.run(3)
+    want = orc.slot_energies()
+    print(f"\n[case] pair-per-thread energy N={n}: max |diff| {np.max(np.abs(e1 - want)):.3e}, "
+          f"bound {b1.max():.3e}, kernel {ms:.3f} ms", flush=True)
+    assert np.array_equal(e0, want) and np.array_equal(exact, want)
+    assert np.all(b0 > 0) and np.all(b1 > 0)
+    assert np.all(np.abs(e1 - want) <= b1 + b0)
+    assert np.all(np.abs(e1 - want) <= 1e-12 * np.maximum(1.0, np.abs(want)))
