@@ -136,7 +136,7 @@ def cpu_baseline(w, budget_s=12.0, threads=None):
 
 def paper_protocol(n_beads=55, sweeps=4000, every=1000, edge=0.02,
                    replicas=(1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)):
-    """The benchmark of the paper's Sec. 5 on this GPU: one chain of N = 55,
+    """The benchmark of the paper's Sec. 4.2 on this GPU: one chain of N = 55,
     displacement edge 0.02, 4000 sweeps, an exchange step every 1000 sweeps, as
     a function of the number of replicas n_r.  t_GPU includes set-up, the
     host-to-device copies, the sweeps and the read-back of every conformation
