@@ -414,7 +414,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 acc = !broken & sure_acc;
                 de_used = dem;
                 bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
-                exact = __builtin_amdgcn_readfirstlane(sure ? 0 : 1) != 0;
+                exact = __builtin_amdgcn_ballot_w64(!sure) != 0;  // uniform: a scalar branch
                 n_rescore += exact ? 1 : 0;
             }
             if (exact) {
@@ -437,7 +437,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 de_used = de;
                 bm = bound64(log2c(n), ab, dfl, dfr, de);
             }
-            if (__builtin_amdgcn_readfirstlane(acc ? 1 : 0) != 0) {
+            if (__builtin_amdgcn_ballot_w64(acc) != 0) {
                 if (mine) {
                     const int ak = G::pos(k);
                     X[ak] = xn;
