@@ -36,10 +36,13 @@
  *   (m,t,g,1) -> v0;  k = floor(w0*N/2^32);  d_a = (((w_a+.5)2^-32)-.5)*edge;
  *   u = (v0+.5)2^-32;
  *   exchange of slots (i,i+1) of stream chain c at step e: counter (i,e,c,2).
- * PT_FP64 evaluates the pair terms in that order.  PT_MIXED evaluates them in
- * FP32 from r^2 formed in FP64 from FP64 separations (r^2 clamped at the
- * cutoff), sums them in FP32 as the same pairwise tree (so every output is
- * independent of the mapping), adds the FP64 bond terms in FP64, and re-scores
+ * PT_FP64 evaluates the pair terms in that order.  PT_MIXED evaluates the
+ * bracket s6*(s6-1) of each pair in FP32 from r^2 formed in FP64 from the FP64
+ * separation (r^2 clamped at the cutoff), sums the
+ * differences of new and old brackets in FP32 as the same pairwise tree (so
+ * every output is independent of the mapping) and scales the sum by 4 eps
+ * (the shift E_LJ(rc) cancels in each difference), adds the FP64 bond terms
+ * in FP64, and re-scores
  * in the FP64 order every decision that a rigorous error bound cannot settle;
  * its running energies carry that bound and are re-synchronised with the FP64
  * energy whenever an exchange decision needs it.  At the end of a sweep the running
@@ -282,8 +285,10 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_
 /* Diagnostics of the device arithmetic (used by the test suite).  op:
  *   0: IEEE sqrt      1: IEEE x/y        2: deterministic log
  *   3: FENE term of r2 = x                4: LJ term of r2 = x (FP64 order)
- *   5: FP32 LJ term of r2 from the separation (x, y, 0): out[2i] = value,
- *      out[2i+1] = its error bound (same bound the mixed path uses)
+ *   5: FP32 LJ term of the separation (x, y, 0) as PT_MIXED scores a pair
+ *      whose old separation lies on the cutoff: out[2i] = 4 eps (g(r^2) -
+ *      g(rc^2)) with g the FP32 bracket (= E_mod of Eq. 1 up to rounding),
+ *      out[2i+1] = the error bound the mixed path uses for that pair
  *   6: Philox block: x = counter words (4 per item, as doubles), y[0], y[1] =
  *      seed low and high 32 bits (as doubles); out[4i..4i+3] = words
  *   7: FP64 pairwise tree over each group of 64 consecutive x (the wavefront

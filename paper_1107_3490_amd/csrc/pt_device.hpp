@@ -111,45 +111,41 @@ __device__ __forceinline__ double fene64(const Consts &k, double r2) {
     return (y > 0.0) ? v : __builtin_inf();
 }
 
-// FP32 Lennard-Jones term from an FP64 separation, and s6 = (sigma^2/r^2)^3,
-// whose b = s6^2 + s6 bounds the term's error.  r^2 is formed in FP64 from the
-// FP64 separation and rounded to FP32 once; beyond the cutoff r^2 is clamped
-// to the cutoff, where the term is zero up to the rounding of the shift, and
-// both evaluations of a far pair give the same value, so their difference is
-// an exact zero.  With u = 2^-24 and relative errors to first order: r^2 is
-// within 1.01u; v_rcp_f32 (1 ulp, 2u), the conversion of sigma^2 and the
+// FP32 Lennard-Jones bracket g = s6 (s6 - 1), s6 = (sigma^2/r^2)^3, from an
+// r^2 formed in FP64 and rounded to FP32 once, with r^2 clamped to the cutoff:
+// the term of Eqs. (1)-(2) is 4 eps g(min(r^2, rc^2)) - E_LJ(rc), so the
+// difference of a pair's new and old terms is 4 eps times the difference of
+// their brackets (the shift cancels exactly), a far pair gives the same
+// bracket twice and an exact zero, and the kernels sum bracket differences in
+// FP32 and scale the sum by 4 eps once.  Error, with u = 2^-24, relative
+// errors to first order and b = s6^2 + s6 (>= |g|): r^2 is within 1.01u (FP64
+// r^2 rounded to FP32); v_rcp_f32 (1 ulp, 2u), the conversion of sigma^2 and the
 // product give s2 within 5u; s4 11u; s6 17u; fma(s6, s6, -s6) is within
-// (|2 s6 - 1| 17u s6 + u |g|) <= 35u b; the final fma and the conversions of
-// 4 eps and E_LJ(rc) bring the term within 37u (4 eps) b + 2u |E_LJ(rc)|, and
-// the later FP32 difference of the new and old terms adds u (4 eps) b +
-// u |E_LJ(rc)| per term.  For a pair inside the cutoff b >= b_rc =
-// s6(rc)(1 + s6(rc)), so the |E_LJ(rc)| parts are below c_erc u (4 eps) b,
-// c_erc = 3 |E_LJ(rc)| / (4 eps b_rc).  A pair whose FP32 r^2 lands on the
-// other side of the cutoff than the FP64 one is within 2u rc^2 of it, where
-// |E_mod| <= |dE/dr^2|(rc) 2u rc^2 <= c_win u (4 eps) b_rc (c_win is taken
-// for a 6u window).  The kernels sum the FP32 pair terms t of a move in FP32
-// (in-lane tree, butterfly and the tree over wavefronts: a pairwise tree of
-// depth <= 11), which adds at most 11.01u sum |t|; since |E_LJ(rc)| <=
-// (4 eps) b for any pair inside the cutoff, |t| <= 2 (4 eps)(b_new + b_old)
-// (1 + 2^-20), so the sum adds at most 22.1u (4 eps) per unit of b.  The host
-// sets kbound = kappa u (4 eps)(1 + 2^-8), kappa >= 62 + c_erc + c_win with
-// a margin (at least 128; the terms need 39 + c_erc + c_win), plus 24 for the
-// sum.  Per pair the kernels accumulate b' = S^2 + S with S = s6_new + s6_old,
-// which is >= b_new + b_old, inside or outside the cutoff; the FP32 sum of
-// the b' (depth <= 11, at most 11.01u low) is scaled by 1 + 2^-20 before use.
+// (|2 s6 - 1| 17u s6 + u |g|) <= 35u b; the FP32 difference of the new and old
+// brackets adds u (b_new + b_old).  A pair whose FP32 r^2 lands on the other
+// side of the cutoff than the exact one is within 2u rc^2 of it, where
+// |E_mod| <= |dE/dr^2|(rc) 2u rc^2 <= c_win u (4 eps) b_rc (c_win is taken for
+// a 6u window; b >= b_rc = s6(rc)(1 + s6(rc)) inside the cutoff).  The pairwise
+// FP32 sum of a move (in-lane tree, butterfly, tree over wavefronts: depth
+// <= 11) adds at most 11.01u sum |t| <= 11.01u sum (b_new + b_old), and the
+// scaling by 4 eps is exact for a power of two (else one FP64 rounding, inside
+// the decision's relative slack).  Per pair the kernels accumulate
+// b' = S^2 + S with S = s6_new + s6_old (>= b_new + b_old), and use
+// kbound sum b' with kbound = kappa u (4 eps)(1 + 2^-8), kappa >= 128 and
+// >= 1.25 (62 + c_erc + c_win), plus 24 for the sum: the terms need
+// 37 + c_win, so the margin is more than a factor two.
 struct Lj32 {
-    float e;   // term
+    float g;   // bracket s6 (s6 - 1)
     float s6;  // (sigma^2 / r^2)^3 of the (clamped) FP32 r^2
 };
 
-__device__ __forceinline__ Lj32 lj32(const Consts &k, double dx, double dy, double dz) {
-    const double r2d = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+__device__ __forceinline__ Lj32 lj32(const Consts &k, double r2d) {
     const float r2 = __builtin_fminf((float)r2d, k.rc2_f);
     const float q = __builtin_amdgcn_rcpf(r2);
     const float s2 = k.sig2_f * q;
     const float s6 = (s2 * s2) * s2;
     Lj32 o;
-    o.e = __builtin_fmaf(k.four_eps_f, __builtin_fmaf(s6, s6, -s6), -k.e_rc_f);
+    o.g = __builtin_fmaf(s6, s6, -s6);
     o.s6 = s6;
     return o;
 }

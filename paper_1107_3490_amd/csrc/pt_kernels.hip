@@ -380,14 +380,14 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             bool exact = !MIXED;
             if constexpr (MIXED) {
                 const LeafMx s = lane_tree<0, B>([&](int b) {
-                    const Lj32 pn = lj32(K, rx[b] - xn, ry[b] - yn, rz[b] - zn);
-                    const Lj32 po = lj32(K, rx[b] - xo, ry[b] - yo, rz[b] - zo);
+                    const Lj32 pn = lj32(K, sq3(rx[b] - xn, ry[b] - yn, rz[b] - zn));
+                    const Lj32 po = lj32(K, sq3(rx[b] - xo, ry[b] - yo, rz[b] - zo));
                     // The moved bead's own leaf and padding leaves are zeros (a
                     // padding bead's two terms are equal; its bound is dropped so
                     // that the bound does not depend on the padding).
                     const bool skip = (mine && b == slot) || tid * B + b >= n;
                     const float sb = pn.s6 + po.s6;
-                    const float tt = skip ? 0.0f : pn.e - po.e;
+                    const float tt = skip ? 0.0f : pn.g - po.g;
                     const float bb = skip ? 0.0f : __builtin_fmaf(sb, sb, sb);
                     return LeafMx{tt, bb};
                 });
@@ -403,7 +403,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                     bsum = (double)tree_wf<W>(S.part[i & 1][1]);
                 }
                 const double bs = K.kbound * bsum;
-                const double dem = sm + df;
+                const double dem = K.four_eps * sm + df;  // bracket sum -> energy (Eq. 1)
                 const double bt = bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem);
                 const double lo = dem - bt, hi = dem + bt;
                 // Straight-line: every outcome is computed, one is kept.
@@ -1138,9 +1138,13 @@ __global__ void k_selftest(const Consts k, int op, const double *x, const double
         case 3: out[i] = fene64(k, x[i]); break;
         case 4: out[i] = lj64(k, x[i]); break;
         case 5: {
-            const Lj32 r = lj32(k, x[i], y[i], 0.0);
-            out[2 * i] = (double)r.e;
-            out[2 * i + 1] = k.kbound * (double)__builtin_fmaf(r.s6, r.s6, r.s6);
+            // One pair whose old separation lies on the cutoff, as the sweep
+            // scores it: 4 eps (g(r) - g(rc)) and its bound.
+            const Lj32 r = lj32(k, sq3(x[i], y[i], 0.0));
+            const Lj32 c = lj32(k, k.rc2);
+            out[2 * i] = k.four_eps * (double)(r.g - c.g);
+            const float sb = r.s6 + c.s6;
+            out[2 * i + 1] = k.kbound * (double)__builtin_fmaf(sb, sb, sb);
             break;
         }
         case 6: {
