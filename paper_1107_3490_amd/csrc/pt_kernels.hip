@@ -115,46 +115,45 @@ __device__ __forceinline__ double row_chunk(const double *X, const double *Y, co
 }
 
 // FP64-order energy E(C) of Eq. (4) of a replica stored in the swizzled layout
-// (LDS or HBM), on one wavefront (lanes 0..63 of the calling block).  The rows
-// are taken in aligned blocks of 64: lane l computes row 64 r + l, each row
-// being the tree over j in chunks of 16 (static trees chained by a binary
-// counter; chunks left of the block or past the chain end are exact zeros and
-// are skipped); the butterfly over lanes gives the tree over the block's 64
-// rows, and a binary counter over r the tree over all NP rows.  Bonds:
-// contiguous lane blocks and the butterfly.
+// (LDS or HBM).  The rows are taken in aligned blocks of 64: lane l computes
+// row 64 r + l, each row being the tree over j in chunks of 16 (static trees
+// chained by a binary counter; chunks left of the block or past the chain end
+// are exact zeros and are skipped); the butterfly over lanes gives the tree
+// over the block's 64 rows, and a binary counter over r the tree over all NP
+// rows.  Bonds: contiguous lane blocks and the butterfly.
+//
+// Sum of the 64-row block r, on one wavefront.
 template <int B, int W>
-__device__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
-                              const Consts &k) {
+__device__ __forceinline__ double row_block(const double *X, const double *Y, const double *Z, int n,
+                                            const Consts &k, int r) {
     using G = Geo<B, W>;
-    constexpr int BP = B * W;        // 64-row blocks
-    constexpr int LC = ilog2(BP);
     constexpr int CW = 16;           // leaves per chunk
     constexpr int NC = G::NP / CW;   // chunks per row
     constexpr int LR = ilog2(NC);
+    if (r * 64 >= n) return 0.0;
     const int lane = threadIdx.x & 63;
-    double blk[LC + 1];
+    const int i = r * 64 + lane;
+    const int ai = G::pos(i);
+    const double xi = X[ai], yi = Y[ai], zi = Z[ai];
+    double row[LR + 1];
 #pragma unroll
-    for (int l = 0; l <= LC; ++l) blk[l] = 0.0;
-    for (int r = 0; r < BP; ++r) {
-        double bv = 0.0;
-        if (r * 64 < n) {
-            const int i = r * 64 + lane;
-            const int ai = G::pos(i);
-            const double xi = X[ai], yi = Y[ai], zi = Z[ai];
-            double row[LR + 1];
-#pragma unroll
-            for (int l = 0; l <= LR; ++l) row[l] = 0.0;
-            for (int c = 0; c < NC; ++c) {
-                double v = 0.0;
-                if (c * CW + CW > r * 64 && c * CW < n)
-                    v = row_chunk<B, W, 0, CW>(X, Y, Z, k, i, n, c * CW, xi, yi, zi);
-                tree_push<LR>(row, c, v);
-            }
-            bv = wave_tree(row[LR]);
-        }
-        tree_push<LC>(blk, r, bv);
+    for (int l = 0; l <= LR; ++l) row[l] = 0.0;
+    for (int c = 0; c < NC; ++c) {
+        double v = 0.0;
+        if (c * CW + CW > r * 64 && c * CW < n)
+            v = row_chunk<B, W, 0, CW>(X, Y, Z, k, i, n, c * CW, xi, yi, zi);
+        tree_push<LR>(row, c, v);
     }
-    const double e_lj = blk[LC];
+    return wave_tree(row[LR]);
+}
+
+// The bond part, on one wavefront.
+template <int B, int W>
+__device__ __forceinline__ double bonds_wave(const double *X, const double *Y, const double *Z, int n,
+                                             const Consts &k) {
+    using G = Geo<B, W>;
+    constexpr int BP = B * W;
+    const int lane = threadIdx.x & 63;
     const double fb = lane_tree<0, BP>([&](int b) {
         const int i = lane * BP + b;
         const int i0 = (i < n - 1) ? i : 0;
@@ -162,7 +161,53 @@ __device__ double energy_wave(const double *X, const double *Y, const double *Z,
         const double v = fene64(k, sq3(X[a1] - X[a0], Y[a1] - Y[a0], Z[a1] - Z[a0]));
         return (i < n - 1) ? v : 0.0;
     });
-    return e_lj + wave_tree(fb);
+    return wave_tree(fb);
+}
+
+// The whole energy on one wavefront (lanes 0..63 of the calling block).
+template <int B, int W>
+__device__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
+                              const Consts &k) {
+    constexpr int BP = B * W;        // 64-row blocks
+    constexpr int LC = ilog2(BP);
+    double blk[LC + 1];
+#pragma unroll
+    for (int l = 0; l <= LC; ++l) blk[l] = 0.0;
+    for (int r = 0; r < BP; ++r) tree_push<LC>(blk, r, row_block<B, W>(X, Y, Z, n, k, r));
+    return blk[LC] + bonds_wave<B, W>(X, Y, Z, n, k);
+}
+
+// The same energy, bit for bit, with all W wavefronts of the block: wavefront
+// w takes the row blocks r = w, w + W, ..., the last one also the bonds; the
+// block sums meet in LDS (sh: B W + 1 doubles) and every thread chains them
+// with the same binary counter.  Called by every thread of the block; returns
+// the energy in every thread.
+template <int B, int W>
+__device__ double energy_block(const double *X, const double *Y, const double *Z, int n,
+                               const Consts &k, double *sh) {
+    if constexpr (W == 1) {
+        return energy_wave<B, W>(X, Y, Z, n, k);
+    } else {
+        constexpr int BP = B * W;
+        constexpr int LC = ilog2(BP);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int r = wv; r < BP; r += W) {
+            const double bv = row_block<B, W>(X, Y, Z, n, k, r);
+            if (lane == 0) sh[r] = bv;
+        }
+        if (wv == W - 1) {
+            const double fb = bonds_wave<B, W>(X, Y, Z, n, k);
+            if (lane == 0) sh[BP] = fb;
+        }
+        __syncthreads();
+        double blk[LC + 1];
+#pragma unroll
+        for (int l = 0; l <= LC; ++l) blk[l] = 0.0;
+        for (int r = 0; r < BP; ++r) tree_push<LC>(blk, r, sh[r]);
+        const double e = blk[LC] + sh[BP];
+        __syncthreads();  // sh free again
+        return e;
+    }
 }
 
 // Squared end-to-end distance and squared radius of gyration (Eq. 8) of the
@@ -249,6 +294,7 @@ struct SweepLds {
     double part[2][2][W];
     double partx[2][W];
     double bcast[4];
+    double eblk[B * W + 1];  // energy_block
 };
 
 // The N moves of one sweep of the replica held by the block (Sec. 3.2), on
@@ -483,8 +529,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
 // conformation q.  The running energy is first replaced by the FP64-order
 // energy when its bound has grown past resync_rel of max(1, |E|) (a start
 // with near-overlapping beads, or many accepted moves), or after every sweep
-// when the run recomputes the full energy each sweep.  Wavefront 0 does the
-// work; E and Bd leave valid in every thread.
+// when the run recomputes the full energy each sweep, with all wavefronts;
+// wavefront 0 does the rest.  E and Bd leave valid in every thread.
 template <int B, int W>
 __device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S, int g, int q,
                                              int n, int64_t t64, double &E, double &Bd,
@@ -493,20 +539,18 @@ __device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S,
     const double *X = S.xyz, *Y = S.xyz + G::NP, *Z = S.xyz + 2 * G::NP;
     const Consts &K = T.k;
     const int tid = threadIdx.x;
+    // E and Bd are the same in every thread: a block-uniform branch.
+    const bool resync = T.full_energy || !(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0));
+    if (resync) {
+        E = energy_block<B, W>(X, Y, Z, n, K, S.eblk);
+        Bd = bound_energy(K, log2c(n), n, E, 0.0);
+    }
     if (tid < 64) {
         double ree2, rg2;
         shape_wave<B, W>(X, Y, Z, n, ree2, rg2);
-        bool resync = false;
-        if (T.full_energy || !(Bd <= K.resync_rel * (dabs(E) > 1.0 ? dabs(E) : 1.0))) {
-            E = energy_wave<B, W>(X, Y, Z, n, K);
-            Bd = bound_energy(K, log2c(n), n, E, 0.0);
-            resync = true;
-        }
         if (tid == 0) {
             T.e_run[q] = E;
             T.b_run[q] = Bd;
-            S.bcast[0] = E;
-            S.bcast[1] = Bd;
             int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
             cnt[0] += n_acc;
             cnt[3] += n_rescore;
@@ -525,11 +569,6 @@ __device__ __forceinline__ void sweep_record(const Tables &T, SweepLds<B, W> &S,
                 row[2] = rg2;
             }
         }
-    }
-    if constexpr (W > 1) {
-        __syncthreads();
-        E = S.bcast[0];
-        Bd = S.bcast[1];
     }
 }
 
@@ -765,20 +804,22 @@ __global__ __launch_bounds__(64) void k_sweep_lane(const Tables T, const int32_t
 
 // ----------------------------------------------------------------- energy --
 // FP64-order energy of the conformations in `list` (by_slot: list holds slots
-// and the conformation is perm[g]); writes out_e / out_b indexed like list.
+// and the conformation is perm[g]), one block of W wavefronts each; writes
+// out_e / out_b indexed like list.
 template <int B, int W>
-__global__ __launch_bounds__(64) void k_energy(const Tables T, const int32_t *__restrict__ list,
-                                               double *out_e, double *out_b, int by_slot) {
+__global__ __launch_bounds__(64 * W) void k_energy(const Tables T, const int32_t *__restrict__ list,
+                                                   double *out_e, double *out_b, int by_slot) {
     using G = Geo<B, W>;
     __shared__ double XYZ[3 * G::NP];
+    __shared__ double sh[B * W + 1];
     double *const X = XYZ, *const Y = XYZ + G::NP, *const Z = XYZ + 2 * G::NP;
     const int id = list[blockIdx.x];
     const int q = by_slot ? T.perm[id] : id;
     const int c = T.slot_chain[q];  // conformation q started in slot q: same chain
     const int n = T.chain_n[c];
-    copy_replica<B, W, 64>(XYZ, T.coords + T.coord_off[q]);
-    wave_sync();
-    const double e = energy_wave<B, W>(X, Y, Z, n, T.k);
+    copy_replica<B, W, G::NT>(XYZ, T.coords + T.coord_off[q]);
+    __syncthreads();
+    const double e = energy_block<B, W>(X, Y, Z, n, T.k, sh);
     if (threadIdx.x == 0) {
         out_e[id] = e;
         if (out_b != nullptr) out_b[id] = bound_energy(T.k, log2c(n), n, e, 0.0);
@@ -863,8 +904,8 @@ __global__ __launch_bounds__(64 * W) void k_energy_pairs(const Tables T, const i
 // energies e1, e2 and bounds b1, b2.  The decision is taken from the running
 // energies when their bounds settle it; otherwise canon(0), canon(1) give the
 // FP64-order energies of q1 and q2, the decision is exact, and e1, b1, e2, b2
-// are replaced by those energies and their bounds (band = true).  Wavefront-
-// uniform; called by one wavefront.
+// are replaced by those energies and their bounds (band = true).  Block-
+// uniform; called by every thread of the block (canon synchronises it).
 template <int B, int W, class Canon>
 __device__ __forceinline__ bool exch_decide(const Tables &T, int c, int i, int64_t e, int n, int g,
                                             double &e1, double &bb1, double &e2, double &bb2,
@@ -911,13 +952,14 @@ __device__ __forceinline__ void exch_commit(const Tables &T, int g, int64_t e, i
     T.dig[2 * g + 1] = mix64(T.dig[2 * g + 1] ^ (((uint64_t)e << 1) | (acc ? 1u : 0u)));
 }
 
-// One exchange step for the chains in `list`: wavefront p of a chain handles
-// the pair (i, i+1), i = (e mod 2) + 2p.
+// One exchange step for the chains in `list`: block p of a chain (W
+// wavefronts) handles the pair (i, i+1), i = (e mod 2) + 2p.
 template <int B, int W>
-__global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *__restrict__ list,
-                                                 int max_pairs, int force) {
+__global__ __launch_bounds__(64 * W) void k_exchange(const Tables T, const int32_t *__restrict__ list,
+                                                     int max_pairs, int force) {
     using G = Geo<B, W>;
     __shared__ double XYZ[3 * G::NP];
+    __shared__ double sh[B * W + 1];
     const int c = list[blockIdx.x / max_pairs];
     const int p = blockIdx.x % max_pairs;
     const int64_t t = T.te[0], e = T.te[1];
@@ -937,11 +979,12 @@ __global__ __launch_bounds__(64) void k_exchange(const Tables T, const int32_t *
     const double *src1 = T.coords + T.coord_off[q1], *src2 = T.coords + T.coord_off[q2];
     const Consts K = T.k;
     double *const lds = XYZ;
-    auto canon = [lds, src1, src2, n, K](int which) {
-        wave_sync();
-        copy_replica<B, W, 64>(lds, which == 0 ? src1 : src2);
-        wave_sync();
-        return energy_wave<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K);
+    double *const shp = sh;
+    auto canon = [lds, shp, src1, src2, n, K](int which) {
+        __syncthreads();
+        copy_replica<B, W, G::NT>(lds, which == 0 ? src1 : src2);
+        __syncthreads();
+        return energy_block<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K, shp);
     };
     const bool acc = exch_decide<B, W>(T, c, i, e, n, g, e1, bb1, e2, bb2, band, canon);
     if (threadIdx.x == 0) {
@@ -1016,54 +1059,58 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
         const int par = (int)(e & 1);
         const bool lower = i >= par && ((i - par) & 1) == 0 && i + 1 < R;
         const bool upper = i >= 1 + par && ((i - 1 - par) & 1) == 0;
-        if (tid < 64) {
-            int32_t ok = 1, slot = g;
-            if (lower) {
-                if (tid == 0) ok = wait_ge(&T.done[g + 1], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
-                ok = __builtin_amdgcn_readfirstlane(ok);
-                if (ok) {
-                    __threadfence();
-                    const int q2 = T.perm[g + 1];
-                    double e1 = E, bb1 = Bd;
-                    double e2 = T.e_run[q2], bb2 = T.b_run[q2];
-                    bool band = false;
-                    const double *c2 = T.coords + T.coord_off[q2];
-                    double *const lds = S.xyz;
-                    const Consts K = T.k;
-                    auto canon = [lds, c2, cq, n, K](int which) {
-                        if (which == 1) {
-                            wave_sync();
-                            copy_replica<B, W, 64>(lds, c2);
-                            wave_sync();
-                        }
-                        const double v = energy_wave<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K);
-                        if (which == 1) {
-                            wave_sync();
-                            copy_replica<B, W, 64>(lds, cq);
-                            wave_sync();
-                        }
-                        return v;
-                    };
-                    const bool acc = exch_decide<B, W>(T, c, i, e, n, g, e1, bb1, e2, bb2, band, canon);
-                    if (tid == 0) {
-                        if (band) {
-                            T.e_run[q] = e1;
-                            T.b_run[q] = bb1;
-                            T.e_run[q2] = e2;
-                            T.b_run[q2] = bb2;
-                            S.bcast[0] = e1;
-                            S.bcast[1] = bb1;
-                        } else {
-                            S.bcast[0] = E;
-                            S.bcast[1] = Bd;
-                        }
-                        exch_commit(T, g, e, q, q2, acc, band);
-                        __threadfence();
-                        __hip_atomic_store(&T.dec[g + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (lower) {
+            // Every wavefront takes part: the FP64-order energies of a decision
+            // inside the band use the whole block.
+            if (tid == 0) s_ok = wait_ge(&T.done[g + 1], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
+            __syncthreads();
+            if (s_ok) {
+                __threadfence();
+                const int q2 = T.perm[g + 1];
+                double e1 = E, bb1 = Bd;
+                double e2 = T.e_run[q2], bb2 = T.b_run[q2];
+                bool band = false;
+                const double *c2 = T.coords + T.coord_off[q2];
+                double *const lds = S.xyz;
+                double *const shp = S.eblk;
+                const Consts K = T.k;
+                auto canon = [lds, shp, c2, cq, n, K](int which) {
+                    if (which == 1) {
+                        __syncthreads();
+                        copy_replica<B, W, G::NT>(lds, c2);
+                        __syncthreads();
                     }
-                    slot = acc ? g + 1 : g;
+                    const double v = energy_block<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K, shp);
+                    if (which == 1) {
+                        copy_replica<B, W, G::NT>(lds, cq);  // after energy_block's last barrier
+                        __syncthreads();
+                    }
+                    return v;
+                };
+                const bool acc = exch_decide<B, W>(T, c, i, e, n, g, e1, bb1, e2, bb2, band, canon);
+                if (tid == 0) {
+                    if (band) {
+                        T.e_run[q] = e1;
+                        T.b_run[q] = bb1;
+                        T.e_run[q2] = e2;
+                        T.b_run[q2] = bb2;
+                        S.bcast[0] = e1;
+                        S.bcast[1] = bb1;
+                    } else {
+                        S.bcast[0] = E;
+                        S.bcast[1] = Bd;
+                    }
+                    exch_commit(T, g, e, q, q2, acc, band);
+                    __threadfence();
+                    __hip_atomic_store(&T.dec[g + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    s_slot = acc ? g + 1 : g;
                 }
-            } else if (upper) {
+            } else if (tid == 0) {
+                s_slot = g;
+            }
+        } else if (tid < 64) {
+            int32_t ok = 1, slot = g;
+            if (upper) {
                 if (tid == 0) ok = wait_ge(&T.dec[g], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
                 ok = __builtin_amdgcn_readfirstlane(ok);
                 if (ok) {
@@ -1179,7 +1226,7 @@ hipError_t sweep_lane_bw(const Tables &T, const int32_t *list, int n, hipStream_
 template <int B, int W>
 hipError_t energy_bw(const Tables &T, const int32_t *list, int n, double *oe, double *ob, int by_slot,
                      hipStream_t s) {
-    hipLaunchKernelGGL((k_energy<B, W>), dim3(n), dim3(64), 0, s, T, list, oe, ob, by_slot);
+    hipLaunchKernelGGL((k_energy<B, W>), dim3(n), dim3(64 * W), 0, s, T, list, oe, ob, by_slot);
     return hipGetLastError();
 }
 
@@ -1191,7 +1238,7 @@ hipError_t energy_pairs_bw(const Tables &T, const int32_t *list, int n, double *
 
 template <int B, int W>
 hipError_t exchange_bw(const Tables &T, const int32_t *list, int nc, int mp, int force, hipStream_t s) {
-    hipLaunchKernelGGL((k_exchange<B, W>), dim3(nc * mp), dim3(64), 0, s, T, list, mp, force);
+    hipLaunchKernelGGL((k_exchange<B, W>), dim3(nc * mp), dim3(64 * W), 0, s, T, list, mp, force);
     return hipGetLastError();
 }
 
