@@ -60,13 +60,17 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     obs = sim.observables()
+    # Stability of the figure: five more segments of K/5 steps (after the
+    # timed region, not part of it).
+    seg = max(1, steps // 5)
+    repeats = [sim.time_sweeps(seg)[1] / seg for _ in range(5)]
     sim.close()
     pairs = w.pair_interactions_per_sweep() * steps
     return dict(pairs=pairs, wall_s=wall, event_total_ms=total_ms, sweep_kernel_ms=sweep_ms,
                 launches=launches, rescored=int(obs["counts"][:, 3].sum()),
                 moves=int(obs["counts"][:, 5].sum()), exch_recompute=int(obs["counts"][:, 4].sum()),
                 persistent=persistent, mapping=tuned, classes=classes,
-                resyncs=int(obs["counts"][:, 6].sum()))
+                resyncs=int(obs["counts"][:, 6].sum()), repeats_ms_per_step=repeats)
 
 
 def kernel_sources_sha256():
@@ -335,6 +339,9 @@ def main():
                    "pairs_per_step": w.pair_interactions_per_sweep(), "precision": "mixed",
                    "schedule": "persistent" if mixed["persistent"] else "per-sweep",
                    "mapping_N_B_W": mixed["mapping"]},
+        "repeat_segments": {"steps_each": max(1, args.steps // 5),
+                            "ms_per_step": mixed["repeats_ms_per_step"],
+                            "median_ms_per_step": float(np.median(mixed["repeats_ms_per_step"]))},
         "sweeps_per_s": args.steps / (mixed["event_total_ms"] / 1e3),
         "replica_sweeps_per_s": args.steps * slots / (mixed["event_total_ms"] / 1e3),
         "wall_s": mixed["wall_s"],
