@@ -46,7 +46,7 @@
  * in the FP64 order every decision that a rigorous error bound cannot settle;
  * its running energies carry that bound and are re-synchronised with the FP64
  * energy whenever an exchange decision needs it.  At the end of a sweep the running
- * energy is replaced by the FP64-order energy when its bound exceeds 2^-40
+ * energy is replaced by the FP64-order energy when its bound exceeds 2^-30
  * (PT_FP64) or 2^-10 (PT_MIXED) of max(1, |E|).
  *
  * Threading: a handle is not thread-safe.  Separate handles on separate

@@ -147,7 +147,8 @@ pt::Consts make_consts(const pt_model *m, bool mixed) {
     const double kappa = std::max(128.0, ceil(1.25 * (62.0 + c_erc + c_win))) + 24.0;
     k.kbound = kappa * 0x1p-24 * k.four_eps * (1.0 + 0x1p-8);
     k.neg_floor = (m->epsilon + fabs(k.e_rc)) * (1.0 + 0x1p-30);
-    k.resync_rel = mixed ? 0x1p-10 : 0x1p-40;
+    // FP64: 2^-30 < 1e-9, so a running energy stays within 1e-9 of max(1, |E|).
+    k.resync_rel = mixed ? 0x1p-10 : 0x1p-30;
     return k;
 }
 
