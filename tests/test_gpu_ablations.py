@@ -42,7 +42,7 @@ def _oracle(w, sweeps):
                 exch_accepts=orc.exch_accepts, exch_tries=orc.exch_tries)
 
 
-@pytest.mark.parametrize("case", ["uneven", "layouts", "n700"])
+@pytest.mark.parametrize("case", ["uneven", "layouts", "n700", "n2048"])
 def test_lane_per_replica_matches_oracle_and_wavefront_path(case):
     pt = _pt()
     if case == "uneven":
@@ -56,10 +56,15 @@ def test_lane_per_replica_matches_oracle_and_wavefront_path(case):
         w = I.make_workload([100, 100, 100], [4, 4, 4], [(0.2, 1.5)] * 3, "walk", 12, 0, "fp64")
         codes = [pt.PT_MAP_LANE | 0x24, pt.PT_MAP_LANE | 0x42, pt.PT_MAP_LANE | 0x81]
         sweeps = 10
-    else:
+    elif case == "n700":
         w = I.make_workload([700], [4], [(0.3, 1.2)], "walk", 13, 0, "fp64")
         codes = [pt.PT_MAP_LANE | 0x82]
         sweeps = 3
+    else:
+        # the longest chain, in the widest layout
+        w = I.make_workload([2048], [2], [(0.3, 1.2)], "walk", 18, 0, "fp64")
+        codes = [pt.PT_MAP_LANE | 0x84]
+        sweeps = 1
     print(f"\n[case] lane per replica {case}: N={list(w.n_beads)} codes={[hex(c) for c in codes]} "
           f"sweeps={sweeps}", flush=True)
     g = run_gpu(w, sweeps, "fp64", schedule=pt.PT_SCHED_AUTO, mapping=codes)
@@ -79,14 +84,19 @@ def test_lane_per_replica_is_fp64_only():
 
 
 @pytest.mark.parametrize("variant", ["fp64-per-sweep", "fp64-persistent", "mixed-per-sweep",
-                                     "mixed-persistent", "lane"])
+                                     "mixed-persistent", "lane", "mixed-persistent-n2000"])
 def test_full_energy_each_sweep_records_the_fp64_order_energy(variant):
     pt = _pt()
     prec = "mixed" if variant.startswith("mixed") else "fp64"
-    sched = pt.PT_SCHED_PERSISTENT if variant.endswith("persistent") else pt.PT_SCHED_PER_SWEEP
-    w = I.make_workload([13, 55, 100, 300], [6, 6, 6, 4], [(0.2, 1.5)] * 4, "walk", 15, 0, prec)
+    sched = pt.PT_SCHED_PERSISTENT if "persistent" in variant else pt.PT_SCHED_PER_SWEEP
+    if variant.endswith("n2000"):
+        # four wavefronts share every FP64 energy (8 beads per lane)
+        w = I.make_workload([2000], [4], [(0.3, 1.5)], "walk", 19, 0, prec)
+        sweeps = 2
+    else:
+        w = I.make_workload([13, 55, 100, 300], [6, 6, 6, 4], [(0.2, 1.5)] * 4, "walk", 15, 0, prec)
+        sweeps = 8
     mapping = [pt.PT_MAP_LANE | _default_code(n) for n in w.n_beads] if variant == "lane" else None
-    sweeps = 8
     print(f"\n[case] full energy each sweep, {variant}", flush=True)
     g = run_gpu(w, sweeps, prec, schedule=sched | pt.PT_SCHED_FULL_ENERGY, mapping=mapping)
     o = _oracle(w, sweeps)
