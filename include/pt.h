@@ -110,9 +110,9 @@ typedef struct pt_config {
                                        device; 0 = none                                */
     int64_t log_capacity;           /* sweeps of accept bits and exchange outcomes kept
                                        on the device; 0 = none                         */
-    int32_t schedule;               /* PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or
-                                       PT_SCHED_PERSISTENT (same results), optionally
-                                       | PT_SCHED_FULL_ENERGY                          */
+    int32_t schedule;               /* PT_SCHED_AUTO, PT_SCHED_PER_SWEEP,
+                                       PT_SCHED_PERSISTENT or PT_SCHED_FLOW (same
+                                       results), optionally | PT_SCHED_FULL_ENERGY     */
     const int32_t *mapping;         /* [n_chains] 16*B + W (beads per lane B in
                                        {1,2,4,8}, wavefronts per replica W in {1,2,4},
                                        64*W*B >= N), optionally | PT_MAP_LANE, or 0
@@ -124,9 +124,13 @@ typedef struct pt_config {
  * PER_SWEEP: one sweep kernel launch per sweep, then an exchange kernel.
  * PERSISTENT: one launch for all n sweeps; every replica stays on the chip
  * and exchange attempts synchronise the two blocks of a pair only; used when
- * all replicas of the class fit on the device at once (else PER_SWEEP).
- * AUTO = PERSISTENT. */
-enum pt_schedule { PT_SCHED_AUTO = 0, PT_SCHED_PER_SWEEP = 1, PT_SCHED_PERSISTENT = 2 };
+ * all replicas of the class fit on the device at once, else FLOW.
+ * FLOW: one launch for all n sweeps with as many blocks as fit; they take
+ * (sweep, slot) tasks in order, each task sweeping one replica from device
+ * memory, and the task that finishes an attempted pair's sweep second takes
+ * the exchange decision; no block ever waits for a later task.
+ * AUTO = PERSISTENT.  Every schedule gives the same results bit for bit. */
+enum pt_schedule { PT_SCHED_AUTO = 0, PT_SCHED_PER_SWEEP = 1, PT_SCHED_PERSISTENT = 2, PT_SCHED_FLOW = 3 };
 
 /* The paper's alternative designs, kept as measured alternatives (Sec. 3.4,
  * Sec. 4.2); results are unchanged bit for bit.
@@ -277,8 +281,9 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n_sweeps, double *sweep_ms, doub
 
 /* Mapping of each chain (any pointer may be NULL): beads per lane (a power
  * of two <= 8) and wavefronts per replica (1, 2 or 4) -- config.mapping, or
- * by default the smallest pair with 64 * wpr * bpl >= N -- and 1 where the
- * chain's class runs the persistent schedule, else 0.  [n_chains] each. */
+ * by default the smallest pair with 64 * wpr * bpl >= N -- and the schedule
+ * of the chain's class: 1 persistent, 2 task flow, 0 one launch per sweep.
+ * [n_chains] each. */
 PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_per_replica,
                           int32_t *persistent);
 

@@ -49,6 +49,9 @@ struct Tables {
     int64_t *dec;                // persistent runs: exchange steps decided for q's pair
     int32_t *err;                // persistent runs: nonzero after a synchronisation timeout
     uint64_t *dig;               // [S][2] digests of the accept words and exchange outcomes
+    int64_t *flow_ready;         // task flow: slot g's conformation is settled for sweeps < value
+    int64_t *flow_arr;           // task flow: arrivals at the pair whose lower slot is g (2 per attempt)
+    int64_t *flow_task;          // task flow: next task
     // per chain c
     const int32_t *chain_n;      // beads
     const int32_t *chain_slots;  // slots
@@ -94,6 +97,10 @@ hipError_t launch_advance(const Tables &T, int force, hipStream_t s);
 hipError_t launch_run(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *conf_list,
                       int n_items, int64_t n_sweeps, int64_t t0, int64_t e0, int *fits,
                       hipStream_t s);
+// Task flow of n_sweeps sweeps and exchange steps for one class whose slots do
+// not all fit on the device at once (any number of resident blocks).
+hipError_t launch_flow(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *slot_list,
+                       int n_items, int64_t n_sweeps, int64_t t0, int64_t e0, hipStream_t s);
 hipError_t launch_set_te(const Tables &T, int64_t t, int64_t e, hipStream_t s);
 hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y,
                            double *out, int64_t n, hipStream_t s);

@@ -587,8 +587,8 @@ __device__ __forceinline__ void load_regs(const SweepLds<B, W> &S, double (&rx)[
 
 // One sweep of every slot in `list` (one block per slot), then its record.
 // Classes of 1024 or more lanes' worth of beads (64 W B >= 1024) are built for
-// three blocks per CU: the register cap costs a few spills outside the pair
-// loop but hides more latency than it adds (measured on N = 2000).
+// three blocks per CU: more registers at two blocks per CU are slower
+// (measured on N = 2000).
 template <int B, int W, bool MIXED>
 __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_sweep(const Tables T, const int32_t *__restrict__ list) {
     using G = Geo<B, W>;
@@ -1144,6 +1144,123 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
     copy_replica<B, W, G::NT>(cq, S.xyz);
 }
 
+// ------------------------------------------------------------- task flow --
+// n_sweeps sweeps and exchange steps of the S slots in `list` when they do not
+// all fit on the device at once: the resident blocks take tasks k = 0, 1, ...
+// from a counter, task k being sweep t0 + k / S of slot list[k mod S].  A
+// task first waits until the slot's conformation for that sweep is settled
+// (ready[g] >= t: the exchange step after the previous sweep decided, or none
+// due), sweeps it from HBM like k_sweep, records it and writes it back.  When
+// an exchange step follows, the two tasks of an attempted pair each publish
+// and count their arrival on the lower slot (arr, two per attempt); the one
+// that arrives second decides exactly as k_exchange does, from the published
+// running energies (FP64-order energies from HBM inside the band), and marks
+// both slots ready.  A task waits only for tasks handed out before it, so the
+// blocks always progress; every wait is bounded as in k_run.
+template <int B, int W, bool MIXED>
+__global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Tables T,
+                                                                       const int32_t *__restrict__ list,
+                                                                       int n_items, int64_t n_sweeps,
+                                                                       int64_t t0, int64_t e0) {
+    using G = Geo<B, W>;
+    __shared__ SweepLds<B, W> S;
+    __shared__ int64_t s_task;
+    __shared__ int32_t s_flag;
+    const int tid = threadIdx.x;
+    const int64_t total = n_sweeps * (int64_t)n_items;
+    const int every = T.exchange_every;
+    for (;;) {
+        if (tid == 0) {
+            const bool failed = __hip_atomic_load(T.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            s_task = failed ? total : __hip_atomic_fetch_add(T.flow_task, (int64_t)1, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const int64_t k = s_task;
+        if (k >= total) return;
+        const int64_t s = k / n_items;
+        const int g = list[k - s * n_items];
+        const int64_t t64 = t0 + s;
+        const int c = T.slot_chain[g];
+        const int n = T.chain_n[c];
+        // The slot's conformation for sweep t64.
+        if (s > 0) {
+            if (tid == 0) s_flag = wait_ge(&T.flow_ready[g], t64, T.err, T.spin_limit) ? 1 : 0;
+            __syncthreads();
+            if (!s_flag) return;  // a timeout: the error flag is set
+            __threadfence();
+        }
+        const int q = T.perm[g];
+        double *cq = T.coords + T.coord_off[q];
+        copy_replica<B, W, G::NT>(S.xyz, cq);
+        __syncthreads();
+        double rx[B], ry[B], rz[B];
+        load_regs<B, W>(S, rx, ry, rz);
+        double E = T.e_run[q], Bd = T.b_run[q];
+        int64_t n_acc = 0, n_rescore = 0;
+        sweep_moves<B, W, MIXED>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
+        copy_replica<B, W, G::NT>(cq, S.xyz);
+        sweep_record<B, W>(T, S, g, q, n, t64, E, Bd, n_acc, n_rescore);
+        // The exchange step after this sweep, if one is due: its index e counts
+        // the due sweeps before t64 since t0.
+        const bool due = every > 0 && (t64 + 1) % every == 0;
+        const int64_t e = due ? e0 + (t64 / every - t0 / every) : 0;
+        const int R = T.chain_slots[c];
+        const int i = g - T.chain_slot0[c];
+        const int par = (int)(e & 1);
+        const bool lower = due && i >= par && ((i - par) & 1) == 0 && i + 1 < R;
+        const bool upper = due && i >= 1 + par && ((i - 1 - par) & 1) == 0;
+        __threadfence();  // coordinates, running energy and record published
+        __syncthreads();
+        if (!lower && !upper) {
+            if (tid == 0) __hip_atomic_store(&T.flow_ready[g], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        const int glow = lower ? g : g - 1;
+        if (tid == 0) {
+            const int64_t old = __hip_atomic_fetch_add(&T.flow_arr[glow], (int64_t)1, __ATOMIC_ACQ_REL,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            s_flag = (int32_t)(old & 1);  // 1: the partner has arrived, this task decides
+        }
+        __syncthreads();
+        if (!s_flag) continue;
+        __threadfence();
+        const int q1 = T.perm[glow], q2 = T.perm[glow + 1];
+        double e1 = T.e_run[q1], bb1 = T.b_run[q1];
+        double e2 = T.e_run[q2], bb2 = T.b_run[q2];
+        bool band = false;
+        const double *c1 = T.coords + T.coord_off[q1], *c2 = T.coords + T.coord_off[q2];
+        double *const lds = S.xyz;
+        double *const shp = S.eblk;
+        const Consts K = T.k;
+        auto canon = [lds, shp, c1, c2, n, K](int which) {
+            __syncthreads();
+            copy_replica<B, W, G::NT>(lds, which == 0 ? c1 : c2);
+            __syncthreads();
+            return energy_block<B, W>(lds, lds + G::NP, lds + 2 * G::NP, n, K, shp);
+        };
+        const bool acc = exch_decide<B, W>(T, c, glow - T.chain_slot0[c], e, n, glow, e1, bb1, e2, bb2, band, canon);
+        if (tid == 0) {
+            if (band) {
+                T.e_run[q1] = e1;
+                T.b_run[q1] = bb1;
+                T.e_run[q2] = e2;
+                T.b_run[q2] = bb2;
+            }
+            exch_commit(T, glow, e, q1, q2, acc, band);
+            __threadfence();
+            __hip_atomic_store(&T.flow_ready[glow], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&T.flow_ready[glow + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+// Reset of the task counter of k_flow (a kernel, not a memset: safe to capture).
+__global__ void k_flow_reset(const Tables T) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *T.flow_task = 0;
+}
+
 // Advance the run counters after a sweep (t += 1, and e += 1 when an exchange
 // step was due) or after an explicit exchange step (e += 1 only).
 __global__ void k_advance(const Tables T, int exchange_only) {
@@ -1260,6 +1377,29 @@ hipError_t run_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64
     return hipLaunchCooperativeKernel(f, dim3(n), dim3(64 * W), args, 0, s);
 }
 
+template <int B, int W>
+hipError_t flow_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64_t n_sweeps,
+                   int64_t t0, int64_t e0, hipStream_t s) {
+    const void *f = mixed ? (const void *)k_flow<B, W, true> : (const void *)k_flow<B, W, false>;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, 0);
+    if (err != hipSuccess) return err;
+    if (n <= 0 || n_sweeps <= 0) return hipSuccess;
+    const int64_t tasks = n_sweeps * (int64_t)n;
+    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+    const unsigned grid = (unsigned)(tasks < resident ? tasks : resident);
+    hipLaunchKernelGGL(k_flow_reset, dim3(1), dim3(64), 0, s, T);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (mixed)
+        hipLaunchKernelGGL((k_flow<B, W, true>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps, t0, e0);
+    else
+        hipLaunchKernelGGL((k_flow<B, W, false>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps, t0, e0);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // The (beads per lane, wavefronts per replica) classes the library builds.
@@ -1325,6 +1465,13 @@ hipError_t launch_run(int bpl, int wpr, bool mixed, const Tables &T, const int32
 #define PT_RUN(B, W) run_bw<B, W>(mixed, T, list, n, n_sweeps, t0, e0, fits, s)
     PT_DISPATCH(bpl, wpr, PT_RUN)
 #undef PT_RUN
+}
+
+hipError_t launch_flow(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
+                       int64_t n_sweeps, int64_t t0, int64_t e0, hipStream_t s) {
+#define PT_FL(B, W) flow_bw<B, W>(mixed, T, list, n, n_sweeps, t0, e0, s)
+    PT_DISPATCH(bpl, wpr, PT_FL)
+#undef PT_FL
 }
 
 hipError_t launch_advance(const Tables &T, int exchange_only, hipStream_t s) {

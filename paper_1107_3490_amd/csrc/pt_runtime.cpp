@@ -71,6 +71,7 @@ struct Layout {
     size_t o_coord_off, o_e_run, o_b_run, o_coords, o_slot_of, o_done, o_dec, o_err;
     size_t o_chain_n, o_chain_slots, o_chain_slot0, o_chain_sid;
     size_t o_te, o_lists, o_tmp, o_alog, o_elog, o_series, o_dig;
+    size_t o_flow_ready, o_flow_arr, o_flow_task;
     size_t bytes = 0;
     int64_t log_cap = 0, series_cap = 0;
     int lists_len = 0;
@@ -90,9 +91,9 @@ int validate(const pt_model *m, const pt_config *c) {
     if (c->exchange_every < 0) return fail(PT_EINVAL, "exchange_every must be >= 0");
     if (c->series_capacity < 0 || c->log_capacity < 0) return fail(PT_EINVAL, "capacities must be >= 0");
     const int sched = c->schedule & ~PT_SCHED_FULL_ENERGY;
-    if (sched < PT_SCHED_AUTO || sched > PT_SCHED_PERSISTENT)
-        return fail(PT_EINVAL, "schedule must be PT_SCHED_AUTO, PT_SCHED_PER_SWEEP or PT_SCHED_PERSISTENT, "
-                               "optionally with PT_SCHED_FULL_ENERGY");
+    if (sched < PT_SCHED_AUTO || sched > PT_SCHED_FLOW)
+        return fail(PT_EINVAL, "schedule must be PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT or "
+                               "PT_SCHED_FLOW, optionally with PT_SCHED_FULL_ENERGY");
     int64_t total = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
         if (c->n_beads[ch] < 2) return fail(PT_EINVAL, "chain %d: n_beads must be >= 2", ch);
@@ -208,6 +209,9 @@ Layout plan(const pt_config *c) {
     L.o_chain_sid = take(4 * C);
     L.o_te = take(16);
     L.o_dig = take(16 * S);
+    L.o_flow_ready = take(8 * S);
+    L.o_flow_arr = take(8 * S);
+    L.o_flow_task = take(16);
     L.o_lists = take(4 * (size_t)L.lists_len);
     L.o_tmp = take(16 * S);
     L.o_alog = take(8 * (size_t)L.words_total * (size_t)L.log_cap);
@@ -232,6 +236,8 @@ struct Class {
     int bpl = 0, wpr = 0;
     bool lane = false;        // one lane per replica (FP64 order, per-sweep launches)
     bool persistent = false;  // whole sweeps run by one cooperative launch
+    bool flow = false;        // whole sweeps run by one task-flow launch (slots do not all fit)
+    bool whole() const { return persistent || flow; }
     int n_slots = 0, n_chains = 0, max_pairs = 0;
     int32_t *d_slots = nullptr;   // slot (= starting conformation) list
     int32_t *d_chains = nullptr;  // chain list
@@ -253,7 +259,7 @@ struct pt_handle {
     hipGraphExec_t graph1 = nullptr, graph16 = nullptr;
     double *d_tmp = nullptr;
     uint64_t seed = 0;
-    bool failed = false;  // a persistent run timed out; only pt_set_state recovers
+    bool failed = false;  // a persistent or task-flow run timed out; only pt_set_state recovers
 };
 
 namespace {
@@ -265,12 +271,12 @@ hipError_t launch_class_sweep(const pt_handle *h, const Class &c, hipStream_t s)
 
 int enqueue_sweep(pt_handle *h, hipStream_t s) {
     for (const Class &c : h->classes) {
-        if (c.persistent) continue;
+        if (c.whole()) continue;
         hipError_t e = launch_class_sweep(h, c, s);
         if (e != hipSuccess) return fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e));
     }
     for (const Class &c : h->classes) {
-        if (c.persistent) continue;
+        if (c.whole()) continue;
         hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, s);
         if (e != hipSuccess) return fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
     }
@@ -397,6 +403,9 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.dec = (int64_t *)(w + L.o_dec);
     T.err = (int32_t *)(w + L.o_err);
     T.dig = (uint64_t *)(w + L.o_dig);
+    T.flow_ready = (int64_t *)(w + L.o_flow_ready);
+    T.flow_arr = (int64_t *)(w + L.o_flow_arr);
+    T.flow_task = (int64_t *)(w + L.o_flow_task);
     T.accept_log = L.log_cap > 0 ? (uint64_t *)(w + L.o_alog) : nullptr;
     T.log_cap = L.log_cap;
     T.words_total = L.words_total;
@@ -467,6 +476,9 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_dec, 0, 8 * (size_t)S, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_err, 0, 16, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_dig, 0, 16 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_flow_ready, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_flow_arr, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.o_flow_task, 0, 16, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.o_counts, 0, 8 * pt::PT_NCOUNTS * (size_t)S, h->stream);
     if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_elog, 0xFF, (size_t)S * L.log_cap, h->stream);
     if (e == hipSuccess && L.log_cap > 0) e = hipMemsetAsync(w + L.o_alog, 0, 8 * (size_t)L.words_total * L.log_cap, h->stream);
@@ -478,14 +490,19 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     }
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "initialisation failed: %s", hipGetErrorString(e)));
-    // Persistent schedule for every class whose replicas fit on the device at once.
-    if ((cfg->schedule & ~PT_SCHED_FULL_ENERGY) != PT_SCHED_PER_SWEEP) {
+    // Persistent schedule for every class whose replicas fit on the device at
+    // once, the task flow for the others (or for all with PT_SCHED_FLOW).
+    const int sched = cfg->schedule & ~PT_SCHED_FULL_ENERGY;
+    if (sched != PT_SCHED_PER_SWEEP) {
         for (Class &cl : h->classes) {
             if (cl.lane) continue;
-            int fits = 0;
-            e = pt::launch_run(cl.bpl, cl.wpr, h->mixed, T, cl.d_slots, cl.n_slots, 0, 0, 0, &fits, h->stream);
-            if (e != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e)));
-            cl.persistent = fits != 0;
+            if (sched != PT_SCHED_FLOW) {
+                int fits = 0;
+                e = pt::launch_run(cl.bpl, cl.wpr, h->mixed, T, cl.d_slots, cl.n_slots, 0, 0, 0, &fits, h->stream);
+                if (e != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e)));
+                cl.persistent = fits != 0;
+            }
+            cl.flow = !cl.persistent;
         }
     }
     e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
@@ -494,17 +511,23 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     return PT_OK;
 }
 
-// Persistent classes: one cooperative launch each covers all n sweeps,
+// Persistent and task-flow classes: one launch each covers all n sweeps,
 // exchanges included.  With ev, brackets every launch with an event pair.
 int enqueue_persistent(pt_handle *h, int64_t n, std::vector<hipEvent_t> *ev, size_t *k) {
     for (const Class &c : h->classes) {
-        if (!c.persistent) continue;
+        if (!c.whole()) continue;
         if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k], h->stream));
-        int fits = 0;
-        hipError_t e = pt::launch_run(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, h->t_host,
-                                      h->e_host, &fits, h->stream);
-        if (e != hipSuccess) return fail(PT_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
-        if (!fits) return fail(PT_EHIP, "persistent class no longer fits on the device");
+        if (c.persistent) {
+            int fits = 0;
+            hipError_t e = pt::launch_run(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, h->t_host,
+                                          h->e_host, &fits, h->stream);
+            if (e != hipSuccess) return fail(PT_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
+            if (!fits) return fail(PT_EHIP, "persistent class no longer fits on the device");
+        } else {
+            hipError_t e = pt::launch_flow(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, h->t_host,
+                                           h->e_host, h->stream);
+            if (e != hipSuccess) return fail(PT_EHIP, "task-flow launch failed: %s", hipGetErrorString(e));
+        }
         if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k + 1], h->stream));
         if (k) ++*k;
     }
@@ -513,7 +536,7 @@ int enqueue_persistent(pt_handle *h, int64_t n, std::vector<hipEvent_t> *ev, siz
 
 bool any_per_sweep(const pt_handle *h) {
     for (const Class &c : h->classes)
-        if (!c.persistent) return true;
+        if (!c.whole()) return true;
     return false;
 }
 
@@ -569,7 +592,7 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
     if (h->failed) return fail(PT_ESTATE, "the handle failed earlier; restore a state with pt_set_state");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
     size_t per = 0, pers = 0;
-    for (const Class &c : h->classes) (c.persistent ? pers : per) += 1;
+    for (const Class &c : h->classes) (c.whole() ? pers : per) += 1;
     const size_t nev = pers + (size_t)n * per;
     std::vector<hipEvent_t> ev(2 * nev + 2, nullptr);
     for (auto &x : ev) PT_HIP(hipEventCreate(&x));
@@ -579,7 +602,7 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
     if (n > 0) rc = enqueue_persistent(h, n, &ev, &k);
     for (int64_t i = 0; i < n && rc == PT_OK && per > 0; ++i) {
         for (const Class &c : h->classes) {
-            if (c.persistent) continue;
+            if (c.whole()) continue;
             PT_HIP(hipEventRecord(ev[2 * k], h->stream));
             hipError_t e = launch_class_sweep(h, c, h->stream);
             if (e != hipSuccess) { rc = fail(PT_EHIP, "sweep launch failed: %s", hipGetErrorString(e)); break; }
@@ -587,7 +610,7 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
             ++k;
         }
         for (const Class &c : h->classes) {
-            if (c.persistent || rc != PT_OK) continue;
+            if (c.whole() || rc != PT_OK) continue;
             hipError_t e = pt::launch_exchange(c.bpl, c.wpr, h->T, c.d_chains, c.n_chains, c.max_pairs, 0, h->stream);
             if (e != hipSuccess) rc = fail(PT_EHIP, "exchange launch failed: %s", hipGetErrorString(e));
         }
@@ -629,7 +652,7 @@ int check_err(pt_handle *h) {
     PT_HIP(hipStreamSynchronize(h->stream));
     if (err != 0) {
         h->failed = true;
-        return fail(PT_EHIP, "a persistent run timed out waiting for an exchange partner");
+        return fail(PT_EHIP, "a persistent or task-flow run timed out waiting for an exchange partner");
     }
     return PT_OK;
 }
@@ -773,7 +796,7 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr, int32_t *per
             persistent[c] = 0;
             for (const Class &cl : h->classes)
                 if (cl.bpl == h->L.bpl[c] && cl.wpr == h->L.wpr[c] && cl.lane == (h->L.lane[c] != 0))
-                    persistent[c] = cl.persistent ? 1 : 0;
+                    persistent[c] = cl.persistent ? 1 : cl.flow ? 2 : 0;
         }
     }
     return PT_OK;
@@ -961,8 +984,11 @@ PT_API int pt_set_state(pt_handle *h, const void *buf, size_t bytes) {
     if (e == hipSuccess) e = up(h->L.o_counts, counts, 8 * pt::PT_NCOUNTS * (size_t)S);
     if (e == hipSuccess) e = up(h->L.o_dig, dig, 16 * (size_t)S);
     if (e == hipSuccess) e = up(h->L.o_te, te, 16);
-    // Pair flags of the persistent schedule are keyed by sweep index: clear them.
+    // Pair flags of the persistent schedule are keyed by sweep index, the task
+    // flow's by sweep index and arrival count: clear them.
     if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_done, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_flow_ready, 0, 8 * (size_t)S, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_flow_arr, 0, 8 * (size_t)S, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_dec, 0, 8 * (size_t)S, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + h->L.o_err, 0, 16, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

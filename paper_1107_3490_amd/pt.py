@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libpt.so")
 
 PT_OK, PT_EINVAL, PT_EDOMAIN, PT_ENOMEM, PT_EHIP, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PT_FP64, PT_MIXED = 0, 1
-PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT = 0, 1, 2
+PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT, PT_SCHED_FLOW = 0, 1, 2, 3
 # The paper's alternative designs (see include/pt.h): or-ed into the schedule
 # (full energy after every sweep) or into a chain's mapping code (one lane per
 # replica, FP64 only).
@@ -378,7 +378,8 @@ class Simulation:
         return pt_time_sweeps(self.h, n)
 
     def mapping(self):
-        """(beads per lane, wavefronts per replica, persistent flag) per chain."""
+        """(beads per lane, wavefronts per replica, schedule: 1 persistent, 2 task flow,
+        0 per sweep) per chain."""
         return pt_get_mapping(self.h, len(self.w.n_beads))
 
     def digests(self) -> np.ndarray:

@@ -266,11 +266,13 @@ def _assert_same_state(a, b):
     assert a["obs"]["t"] == b["obs"]["t"] and a["obs"]["e"] == b["obs"]["e"]
 
 
+@pytest.mark.parametrize("schedule", [2, 3])
 @pytest.mark.parametrize("case", ["c1", "c4", "uneven_every3", "n2048", "n700_odd"])
-def test_persistent_schedule_equals_per_sweep(case):
+def test_persistent_schedule_equals_per_sweep(case, schedule):
     """The persistent kernel (one launch, pairwise exchange synchronisation)
-    leaves every output bit-identical to one sweep launch plus one exchange
-    launch per sweep, also when the run is split over several calls."""
+    and the task flow (one launch, tasks taken in order, the later of a pair
+    deciding) leave every output bit-identical to one sweep launch plus one
+    exchange launch per sweep, also when the run is split over several calls."""
     if case == "c1":
         w, sweeps, prec, chunks = I.named("c1"), 400, "mixed", [1, 150, 249]
     elif case == "c4":
@@ -285,10 +287,22 @@ def test_persistent_schedule_equals_per_sweep(case):
     else:
         w = I.make_workload([700], [9], [(0.2, 2.0)], "walk", 18, 0, "fp64")
         sweeps, prec, chunks = 4, "fp64", [4]
-    print(f"\n[case] schedules {case}: slots={w.total_slots} sweeps={sweeps} {prec}", flush=True)
+    print(f"\n[case] schedules {case} ({schedule}): slots={w.total_slots} sweeps={sweeps} {prec}", flush=True)
     a = run_gpu(w, sweeps, prec, schedule=1)
-    b = run_gpu(w, sweeps, prec, schedule=2, chunks=chunks)
-    assert np.all(a["persistent"] == 0) and np.all(b["persistent"] == 1)
+    b = run_gpu(w, sweeps, prec, schedule=schedule, chunks=chunks)
+    assert np.all(a["persistent"] == 0) and np.all(b["persistent"] == (1 if schedule == 2 else 2))
+    _assert_same_state(a, b)
+
+
+def test_flow_runs_classes_that_do_not_fit():
+    """1024 replicas of N = 2000 do not fit on the device at once: the default
+    schedule runs them as a task flow, with outputs bit-identical to one launch
+    per sweep (the uneven start of the flow's tasks across sweeps included)."""
+    w = I.make_workload([2000], [1024], [(0.3, 2.5)], "walk", 21, 0, "mixed")
+    print(f"\n[case] task flow, 1024 replicas of N = 2000, 3 sweeps", flush=True)
+    a = run_gpu(w, 3, "mixed", schedule=1)
+    b = run_gpu(w, 3, "mixed", schedule=0, chunks=[1, 2])
+    assert np.all(a["persistent"] == 0) and np.all(b["persistent"] == 2)
     _assert_same_state(a, b)
 
 
@@ -459,17 +473,18 @@ def test_thirteen_bead_transitions_where_the_paper_has_them():
     assert 0.75 <= t_rg <= 1.25
 
 
-def test_persistent_wait_timeout_fails_cleanly_and_recovers():
-    """A persistent run whose partner waits give up after one poll: every block
-    still exits, the next synchronising call reports PT_EHIP, further sweeps
-    PT_ESTATE, and loading a saved state restores a run that goes on exactly
-    like an undisturbed one."""
+@pytest.mark.parametrize("schedule", [2, 3])
+def test_persistent_wait_timeout_fails_cleanly_and_recovers(schedule):
+    """A persistent or task-flow run whose waits give up after one poll: every
+    block still exits, the next synchronising call reports PT_EHIP, further
+    sweeps PT_ESTATE, and loading a saved state restores a run that goes on
+    exactly like an undisturbed one."""
     pt = _pt()
     w = I.make_workload([60], [16], [(0.2, 1.5)], "walk", 63, 0, "mixed")
-    print("\n[case] persistent timeout, 16 slots, spin limit 1", flush=True)
-    ref = pt.Simulation(w, schedule=2)
+    print(f"\n[case] timeout of schedule {schedule}, 16 slots, spin limit 1", flush=True)
+    ref = pt.Simulation(w, schedule=schedule)
     ref.sweep(30)
-    a = pt.Simulation(w, schedule=2)
+    a = pt.Simulation(w, schedule=schedule)
     a.sweep(10)
     st = a.state()
     a.set_spin_limit(1)
