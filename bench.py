@@ -8,7 +8,8 @@ sweep of N single-monomer moves (each scored against all N-1 other monomers
 plus its bonds), records E, Ree^2 and Rg^2, and one neighbour-temperature
 exchange step follows.  The timed region is K such steps enqueued with HIP
 events around every sweep-kernel launch, bracketed by a synchronize.  Where
-all replicas fit on the chip at once, one persistent launch runs all K steps.
+all replicas fit on the chip at once, one persistent launch runs all K steps;
+where they do not, one task-flow launch does.
 
 Prints one JSON line.  Default workload: one chain of N = 100 monomers,
 64 temperatures geometric in [0.1, 1.5], random-walk start, seed 2.
@@ -52,7 +53,10 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     tuned = sorted({(int(n), int(b), int(v)) + (("lane",) if int(c) & pt.PT_MAP_LANE else ())
                     for n, b, v, c in zip(w.n_beads, bpl, wpr, codes)})
     classes = sorted({(int(b), int(v)) for b, v in zip(bpl, wpr)})
-    persistent = bool(np.all(sim.mapping()[2] == 1))
+    modes = sim.mapping()[2]
+    persistent = bool(np.all(modes == 1))
+    # schedule of each (B, W) class: 1 persistent, 2 task flow, 0 per sweep
+    class_mode = {(int(b), int(v)): int(m) for b, v, m in zip(bpl, wpr, modes)}
     sim.sweep(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -69,7 +73,7 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     return dict(pairs=pairs, wall_s=wall, event_total_ms=total_ms, sweep_kernel_ms=sweep_ms,
                 launches=launches, rescored=int(obs["counts"][:, 3].sum()),
                 moves=int(obs["counts"][:, 5].sum()), exch_recompute=int(obs["counts"][:, 4].sum()),
-                persistent=persistent, mapping=tuned, classes=classes,
+                persistent=persistent, class_mode=class_mode, mapping=tuned, classes=classes,
                 resyncs=int(obs["counts"][:, 6].sum()), repeats_ms_per_step=repeats)
 
 
@@ -204,7 +208,7 @@ def ablations(sweeps=40, warmup=5):
         s.sweep(warmup)
         torch.cuda.synchronize()
         _, total_ms, _ = s.time_sweeps(sweeps)
-        persistent = bool(np.all(s.mapping()[2] == 1))
+        persistent = bool(np.all(s.mapping()[2] != 0))
         s.close()
         return total_ms / sweeps, persistent
 
@@ -263,8 +267,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2],
-                    help="0 auto, 1 one sweep launch per sweep, 2 persistent")
+    ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="0 auto, 1 one sweep launch per sweep, 2 persistent, 3 task flow")
     ap.add_argument("--no-tune", action="store_true", help="default mapping instead of the autotuner's")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for FETCH_SIZE/WRITE_SIZE)")
@@ -305,8 +309,8 @@ def main():
     slots = w.total_slots
     value = mixed["pairs"] / (mixed["event_total_ms"] / 1e3)
     ms_per_step = mixed["event_total_ms"] / args.steps
-    # A persistent launch covers all K sweeps (and their exchange steps); a
-    # per-sweep launch one sweep of one class.  Either way: algorithmic FLOPs
+    # A persistent or task-flow launch covers all K sweeps (and their exchange
+    # steps); a per-sweep launch one sweep of one class.  Either way: algorithmic FLOPs
     # of the timed sweeps over the summed launch time.
     avg_kernel_s = mixed["sweep_kernel_ms"] / 1e3 / mixed["launches"]
     flop_per_launch = FLOP_PER_PAIR * w.pair_interactions_per_sweep() * args.steps / mixed["launches"]
@@ -314,7 +318,8 @@ def main():
     fp64_value = fp64["pairs"] / (fp64["event_total_ms"] / 1e3)
     # The dominant kernel: the one class of the workload, or the most expensive one.
     b_, w_ = max(mixed["classes"], key=lambda c: c[0] * c[1])
-    kernel = f"{'k_run' if mixed['persistent'] else 'k_sweep'}<{b_}, {w_}, true>"
+    mode = mixed["class_mode"][(b_, w_)]
+    kernel = f"{('k_sweep', 'k_run', 'k_flow')[mode]}<{b_}, {w_}, true>"
     # SIMDs a sweep can keep busy: one wavefront per SIMD at most for each of
     # the W wavefronts of every replica (the latency-bound regime).
     waves_of_n = {int(m[0]): int(m[2]) for m in mixed["mapping"]}
@@ -337,7 +342,8 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "slots": slots, "n_beads": sorted(set(w.n_beads)),
                    "pairs_per_step": w.pair_interactions_per_sweep(), "precision": "mixed",
-                   "schedule": "persistent" if mixed["persistent"] else "per-sweep",
+                   "schedule": "+".join(sorted({("per-sweep", "persistent", "task flow")[m]
+                                                for m in mixed["class_mode"].values()})),
                    "mapping_N_B_W": mixed["mapping"]},
         "repeat_segments": {"steps_each": max(1, args.steps // 5),
                             "ms_per_step": mixed["repeats_ms_per_step"],
