@@ -129,8 +129,8 @@ def test_mapping_override_is_validated(L):
 
 
 def test_ablation_flags_are_validated(L):
-    """One lane per replica runs the FP64 order only; the full-energy flag is
-    the only flag the schedule takes."""
+    """One lane per replica runs the FP64 order only; the schedule is one of
+    the four, the full-energy flag the only flag it takes."""
     m = pt.model_struct(I.model_params())
     w = I.make_workload([100], [2], [(0.1, 1.5)], "straight", 1, 0, "fp64")
     cfg, keep = _cfg(w, precision=pt.PT_MIXED)
@@ -142,8 +142,9 @@ def test_ablation_flags_are_validated(L):
     assert L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) > 0
     cfg.mapping = None
     for sched, ok in ((pt.PT_SCHED_FULL_ENERGY, True), (pt.PT_SCHED_PER_SWEEP | pt.PT_SCHED_FULL_ENERGY, True),
-                      (pt.PT_SCHED_PERSISTENT | pt.PT_SCHED_FULL_ENERGY, True), (3, False), (32, False),
-                      (pt.PT_SCHED_FULL_ENERGY | 3, False), (-1, False)):
+                      (pt.PT_SCHED_PERSISTENT | pt.PT_SCHED_FULL_ENERGY, True), (pt.PT_SCHED_FLOW, True),
+                      (pt.PT_SCHED_FLOW | pt.PT_SCHED_FULL_ENERGY, True), (4, False), (32, False),
+                      (pt.PT_SCHED_FULL_ENERGY | 4, False), (-1, False)):
         cfg.schedule = sched
         n = L.pt_workspace_bytes(C.byref(m), C.byref(cfg))
         assert (n > 0) == ok, (sched, n)
