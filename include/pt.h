@@ -174,8 +174,9 @@ PT_API int pt_energy(pt_handle *h, double *h_energy);
 
 /* Energy of each slot's conformation (Eq. 4) by one of two methods,
  * synchronous, [sum R_c] doubles each:
- *   PT_ENERGY_FP64_ORDER: the FP64-order energy of pt_energy (one wavefront
- *     per conformation, one row of pairs per lane); h_bound gets the a-priori
+ *   PT_ENERGY_FP64_ORDER: the FP64-order energy of pt_energy (the wavefronts
+ *     of a conformation's block share its rows of pairs, one row per lane);
+ *     h_bound gets the a-priori
  *     bound on |E - exact sum of the FP64 terms| that the kernels use;
  *   PT_ENERGY_PAIR_PER_THREAD: the paper's parallel energy (Sec. 3.4): the
  *     coordinates in LDS, every thread sums one pair per round, rows i and
@@ -265,10 +266,11 @@ PT_API int pt_get_state(pt_handle *h, void *h_buf, size_t bytes);
 PT_API int pt_set_state(pt_handle *h, const void *h_buf, size_t bytes);
 
 /* Test hook: the number of polls (each a short sleep, about 2^24 by default:
- * seconds) after which a persistent run's wait for an exchange partner gives
- * up.  A small value makes every wait whose partner has not arrived yet time
- * out, which exercises the failure path (PT_EHIP, then PT_ESTATE until
- * pt_set_state) while every block still exits.  Applies to later launches. */
+ * seconds) after which a persistent or task-flow run's wait for an exchange
+ * partner or an earlier task gives up.  A small value makes every wait whose
+ * partner has not arrived yet time out, which exercises the failure path
+ * (PT_EHIP, then PT_ESTATE until pt_set_state) while every block still exits.
+ * Applies to later launches. */
 PT_API int pt_set_spin_limit(pt_handle *h, uint32_t polls);
 
 /* Timing of the sweep kernels: runs n sweeps like pt_sweep, with HIP events

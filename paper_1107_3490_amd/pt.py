@@ -394,5 +394,5 @@ class Simulation:
         pt_set_state(self.h, state)
 
     def set_spin_limit(self, polls: int) -> None:
-        """Test hook for the persistent schedule's bounded partner waits."""
+        """Test hook for the bounded waits of the persistent and task-flow schedules."""
         _check(lib().pt_set_spin_limit(C.c_void_p(self.h), int(polls)))
