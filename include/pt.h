@@ -124,7 +124,8 @@ typedef struct pt_config {
  * PER_SWEEP: one sweep kernel launch per sweep, then an exchange kernel.
  * PERSISTENT: one launch for all n sweeps; every replica stays on the chip
  * and exchange attempts synchronise the two blocks of a pair only; used when
- * all replicas of the class fit on the device at once, else FLOW.
+ * all replicas of the class fit on the device at once, else FLOW for classes
+ * of 1024 or more bead slots per replica (64 W B), else PER_SWEEP.
  * FLOW: one launch for all n sweeps with as many blocks as fit; they take
  * (sweep, slot) tasks in order, each task sweeping one replica from device
  * memory, and the task that finishes an attempted pair's sweep second takes

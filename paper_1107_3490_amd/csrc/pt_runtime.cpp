@@ -42,6 +42,7 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr int kMaxBeads = 2048;      // 4 wavefronts x 64 lanes x 8 beads per lane
 constexpr double kSentinel = 1.0e30; // x coordinate of padding beads (far from everything)
+constexpr int kFlowMinSlots = 1024;  // bead slots per replica from which AUTO picks the task flow
 
 // Mapping of a chain of n beads: beads per lane (a power of two <= 8) and
 // wavefronts per replica (1, 2 or 4), the smallest that cover n.
@@ -491,7 +492,9 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "initialisation failed: %s", hipGetErrorString(e)));
     // Persistent schedule for every class whose replicas fit on the device at
-    // once, the task flow for the others (or for all with PT_SCHED_FLOW).
+    // once; the task flow for the others when their tasks are long (a sweep of
+    // 1024 or more bead slots: shorter tasks pay more for their device-scope
+    // fences and flags than one launch per sweep does); PT_SCHED_FLOW for all.
     const int sched = cfg->schedule & ~PT_SCHED_FULL_ENERGY;
     if (sched != PT_SCHED_PER_SWEEP) {
         for (Class &cl : h->classes) {
@@ -502,7 +505,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
                 if (e != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e)));
                 cl.persistent = fits != 0;
             }
-            cl.flow = !cl.persistent;
+            cl.flow = !cl.persistent && (sched == PT_SCHED_FLOW || 64 * cl.wpr * cl.bpl >= kFlowMinSlots);
         }
     }
     e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
