@@ -380,18 +380,19 @@ def test_digests_fold_the_oracle_decisions():
         assert np.array_equal(got, want), sched
 
 
-def test_checkpoint_resume_is_exact():
+@pytest.mark.parametrize("scheds", [(2, 1), (3, 2), (1, 3)])
+def test_checkpoint_resume_is_exact(scheds):
     """Save after 37 sweeps, restore into a new handle (other schedule and
     precision), run 23 more: everything equals the uninterrupted run."""
     pt = _pt()
     w = I.make_workload([70, 33], [7, 4], [(0.2, 1.5), (0.3, 1.0)], "walk", 62, 0, "mixed",
                         exchange_every=2)
-    print(f"\n[case] checkpoint: slots={w.total_slots}", flush=True)
-    a = pt.Simulation(w, precision="mixed", schedule=2)
+    print(f"\n[case] checkpoint: slots={w.total_slots}, schedules {scheds}", flush=True)
+    a = pt.Simulation(w, precision="mixed", schedule=scheds[0])
     a.sweep(37)
     st = a.state()
     a.sweep(23)
-    b = pt.Simulation(w, precision="fp64", schedule=1)
+    b = pt.Simulation(w, precision="fp64", schedule=scheds[1])
     b.sweep(5)
     b.set_state(st)
     b.sweep(23)
