@@ -368,14 +368,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
         // wavefront, this one possibly not yet to the other wavefronts.
         int last_k = -1;
         double lx = 0.0, ly = 0.0, lz = 0.0;
-        // With one wavefront per replica the next move's record is read one
-        // move ahead (its LDS latency then overlaps the current move); with
-        // more, the registers are worth more than the latency.
-        constexpr bool AHEAD = (W == 1);
-        MoveRec rnext = S.rec[0];
-        for (int i = 0; i < nb; ++i) {
-            const MoveRec r = AHEAD ? rnext : S.rec[i];
-            if constexpr (AHEAD) rnext = S.rec[(i + 1 < MB) ? i + 1 : MB - 1];
+        auto one_move = [&](const int i, const MoveRec &r) {
             const int k = __builtin_amdgcn_readfirstlane(r.k);
             const uint64_t cf =
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r.conflict)) |
@@ -512,6 +505,23 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 last_k = -1;
             }
             wave_sync();
+        };
+        if constexpr (W == 1) {
+            // One wavefront per replica: the next move's record is read while
+            // the current move runs (its LDS latency overlaps the move), in two
+            // alternating register sets, each reloaded only after its move is
+            // done (no copies between them).  With more wavefronts the
+            // registers are worth more than the latency.
+            MoveRec ra = S.rec[0];
+            for (int i = 0; i < nb; i += 2) {
+                const MoveRec rb = S.rec[(i + 1 < MB) ? i + 1 : MB - 1];
+                one_move(i, ra);
+                if (i + 1 >= nb) break;
+                ra = S.rec[(i + 2 < MB) ? i + 2 : MB - 1];
+                one_move(i + 1, rb);
+            }
+        } else {
+            for (int i = 0; i < nb; ++i) one_move(i, S.rec[i]);
         }
         logword |= bits << (m0 & 63);
         if (tid == 0 && (((m0 + MB) & 63) == 0 || m0 + MB >= n)) {
