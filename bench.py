@@ -197,6 +197,9 @@ def ablations(sweeps=40, warmup=5):
       * the full FP64-order energy recomputed after every sweep (the paper's
         per-sweep energy) against the running energy, on the N = 100 and
         N = 500 workloads and the N = 55 chain at 4096 replicas;
+      * mixed precision with every accepted move re-scored in the FP64 order
+        (a running energy as accurate as the FP64 path's) against plain mixed
+        and plain FP64;
       * the paper's one-pair-per-thread energy kernel against the FP64-order
         one (one wavefront per conformation, a row per lane)."""
     import torch
@@ -234,6 +237,14 @@ def ablations(sweeps=40, warmup=5):
                                 "running_energy_ms_per_sweep": run_ms,
                                 "full_energy_ms_per_sweep": full_ms,
                                 "full_over_running": full_ms / run_ms})
+    accept_rows = []
+    for name, w in (("c2", I.named("c2")), ("c3", I.named("c3")), ("N=55 x 4096", chain55(4096))):
+        run_ms, pers = timed(w, "mixed")
+        on_ms, _ = timed(w, "mixed", schedule=pt.PT_SCHED_FP64_ON_ACCEPT)
+        fp64_ms, _ = timed(w, "fp64")
+        accept_rows.append({"workload": name, "persistent": pers, "mixed_ms_per_sweep": run_ms,
+                            "mixed_fp64_on_accept_ms_per_sweep": on_ms, "fp64_ms_per_sweep": fp64_ms,
+                            "on_accept_over_mixed": on_ms / run_ms})
     method_rows = []
     for name, w in (("c2", I.named("c2")), ("c3", I.named("c3")), ("N=55 x 4096", chain55(4096)),
                     ("c5 chain 0 (N=2000 x 256)", I.subset(I.named("c5"), [0]))):
@@ -257,7 +268,8 @@ def ablations(sweeps=40, warmup=5):
     return {"ablations": "paper's alternative designs vs this library's, one MI355X, identical results "
                          "(the pair-per-thread energy: within its rigorous bound)",
             "sweeps": sweeps, "one_lane_per_replica_fp64_N55_edge0.02": lane_rows,
-            "full_energy_every_sweep": energy_rows, "energy_kernels": method_rows}
+            "full_energy_every_sweep": energy_rows, "fp64_on_accept": accept_rows,
+            "energy_kernels": method_rows}
 
 
 def main():

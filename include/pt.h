@@ -47,7 +47,8 @@
  * its running energies carry that bound and are re-synchronised with the FP64
  * energy whenever an exchange decision needs it.  At the end of a sweep the running
  * energy is replaced by the FP64-order energy when its bound exceeds 2^-30
- * (PT_FP64) or 2^-10 (PT_MIXED) of max(1, |E|).
+ * (PT_FP64, and PT_MIXED with PT_SCHED_FP64_ON_ACCEPT) or 2^-10 (PT_MIXED)
+ * of max(1, |E|).
  *
  * Threading: a handle is not thread-safe.  Separate handles on separate
  * streams are independent.  All device work of a handle is enqueued on the
@@ -112,7 +113,8 @@ typedef struct pt_config {
                                        on the device; 0 = none                         */
     int32_t schedule;               /* PT_SCHED_AUTO, PT_SCHED_PER_SWEEP,
                                        PT_SCHED_PERSISTENT or PT_SCHED_FLOW (same
-                                       results), optionally | PT_SCHED_FULL_ENERGY     */
+                                       results), optionally | PT_SCHED_FULL_ENERGY
+                                       and | PT_SCHED_FP64_ON_ACCEPT                 */
     const int32_t *mapping;         /* [n_chains] 16*B + W (beads per lane B in
                                        {1,2,4,8}, wavefronts per replica W in {1,2,4},
                                        64*W*B >= N), optionally | PT_MAP_LANE, or 0
@@ -143,8 +145,14 @@ enum pt_schedule { PT_SCHED_AUTO = 0, PT_SCHED_PER_SWEEP = 1, PT_SCHED_PERSISTEN
  * PT_MAP_LANE (or-ed into a chain's mapping code, precision PT_FP64 only):
  * one lane runs the whole sweep of one replica, 64 replicas per wavefront,
  * coordinates read from and written to device memory bead by bead (the
- * 16*B + W part then only fixes the storage layout); never persistent. */
-enum pt_ablation { PT_SCHED_FULL_ENERGY = 16, PT_MAP_LANE = 0x100 };
+ * 16*B + W part then only fixes the storage layout); never persistent.
+ * PT_SCHED_FP64_ON_ACCEPT (or-ed into config.schedule, PT_MIXED; no effect
+ * with PT_FP64): every accepted move is also re-scored in the FP64 order,
+ * so the running energy adds FP64-order differences only, is re-synchronised
+ * at PT_FP64's threshold and is as accurate as PT_FP64's (the decisions are
+ * the same either way); accepted moves then count as re-scored in
+ * pt_observables. */
+enum pt_ablation { PT_SCHED_FULL_ENERGY = 16, PT_SCHED_FP64_ON_ACCEPT = 32, PT_MAP_LANE = 0x100 };
 
 typedef struct pt_handle pt_handle;
 

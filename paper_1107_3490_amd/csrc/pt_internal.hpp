@@ -70,6 +70,7 @@ struct Tables {
     int32_t exchange_every;
     uint32_t spin_limit;         // polls of a persistent run's partner wait before it gives up
     int32_t full_energy;         // nonzero: every sweep ends with the FP64-order energy
+    int32_t fp64_on_accept;      // nonzero (mixed): accepted moves are re-scored in the FP64 order
     uint64_t seed;
     Consts k;
 };

@@ -317,6 +317,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
     const Consts &K = T.k;
     const double beta = T.beta[g];
     const uint32_t gid = T.slot_gid[g];
+    const bool fp64_on_accept = MIXED && T.fp64_on_accept != 0;
     uint64_t *logrow = (T.accept_log != nullptr && t64 < T.log_cap)
                            ? T.accept_log + t64 * T.words_total + T.word_off[g]
                            : nullptr;
@@ -453,7 +454,10 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 acc = !broken & sure_acc;
                 de_used = dem;
                 bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
-                exact = __builtin_amdgcn_ballot_w64(!sure) != 0;  // uniform: a scalar branch
+                // uniform: a scalar branch; with fp64_on_accept every accepted
+                // move is re-scored as well, so that the running energy adds
+                // FP64-order differences only
+                exact = __builtin_amdgcn_ballot_w64(!sure | (fp64_on_accept & acc)) != 0;
                 n_rescore += exact ? 1 : 0;
             }
             if (exact) {

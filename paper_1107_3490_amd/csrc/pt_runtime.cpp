@@ -43,6 +43,7 @@ int fail(int code, const char *fmt, ...) {
 constexpr int kMaxBeads = 2048;      // 4 wavefronts x 64 lanes x 8 beads per lane
 constexpr double kSentinel = 1.0e30; // x coordinate of padding beads (far from everything)
 constexpr int kFlowMinSlots = 1024;  // bead slots per replica from which AUTO picks the task flow
+constexpr int kSchedFlags = PT_SCHED_FULL_ENERGY | PT_SCHED_FP64_ON_ACCEPT;  // or-ed into a schedule
 
 // Mapping of a chain of n beads: beads per lane (a power of two <= 8) and
 // wavefronts per replica (1, 2 or 4), the smallest that cover n.
@@ -91,10 +92,10 @@ int validate(const pt_model *m, const pt_config *c) {
     if (c->precision != PT_FP64 && c->precision != PT_MIXED) return fail(PT_EINVAL, "precision must be PT_FP64 or PT_MIXED");
     if (c->exchange_every < 0) return fail(PT_EINVAL, "exchange_every must be >= 0");
     if (c->series_capacity < 0 || c->log_capacity < 0) return fail(PT_EINVAL, "capacities must be >= 0");
-    const int sched = c->schedule & ~PT_SCHED_FULL_ENERGY;
+    const int sched = c->schedule & ~kSchedFlags;
     if (sched < PT_SCHED_AUTO || sched > PT_SCHED_FLOW)
         return fail(PT_EINVAL, "schedule must be PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT or "
-                               "PT_SCHED_FLOW, optionally with PT_SCHED_FULL_ENERGY");
+                               "PT_SCHED_FLOW, optionally with PT_SCHED_FULL_ENERGY and PT_SCHED_FP64_ON_ACCEPT");
     int64_t total = 0;
     for (int ch = 0; ch < c->n_chains; ++ch) {
         if (c->n_beads[ch] < 2) return fail(PT_EINVAL, "chain %d: n_beads must be >= 2", ch);
@@ -120,7 +121,7 @@ int validate(const pt_model *m, const pt_config *c) {
 }
 
 // Constants in the fixed expressions of include/pt.h, plus the mixed-path bound.
-pt::Consts make_consts(const pt_model *m, bool mixed) {
+pt::Consts make_consts(const pt_model *m, double resync_rel) {
     pt::Consts k;
     k.sig2 = m->sigma * m->sigma;
     k.rc2 = m->r_cut * m->r_cut;
@@ -149,9 +150,17 @@ pt::Consts make_consts(const pt_model *m, bool mixed) {
     const double kappa = std::max(128.0, ceil(1.25 * (62.0 + c_erc + c_win))) + 24.0;
     k.kbound = kappa * 0x1p-24 * k.four_eps * (1.0 + 0x1p-8);
     k.neg_floor = (m->epsilon + fabs(k.e_rc)) * (1.0 + 0x1p-30);
-    // FP64: 2^-30 < 1e-9, so a running energy stays within 1e-9 of max(1, |E|).
-    k.resync_rel = mixed ? 0x1p-10 : 0x1p-30;
+    k.resync_rel = resync_rel;
     return k;
+}
+
+// A sweep ends with an FP64-order energy when the running energy's bound has
+// passed this fraction of max(1, |E|): 2^-30 (< 1e-9) where the running energy
+// adds FP64-order differences only (PT_FP64, or PT_MIXED with
+// PT_SCHED_FP64_ON_ACCEPT), 2^-10 where it adds FP32 sums.
+double resync_threshold(const pt_config *c) {
+    const bool fp32_sums = c->precision == PT_MIXED && (c->schedule & PT_SCHED_FP64_ON_ACCEPT) == 0;
+    return fp32_sums ? 0x1p-10 : 0x1p-30;
 }
 
 Layout plan(const pt_config *c) {
@@ -327,7 +336,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     if (d_workspace == nullptr || ws_bytes < L.bytes)
         return fail(PT_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.bytes);
     if (((uintptr_t)d_workspace & 255) != 0) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
-    const pt::Consts k = make_consts(model, cfg->precision == PT_MIXED);
+    const pt::Consts k = make_consts(model, resync_threshold(cfg));
 
     // Host-side checks and swizzled coordinates.
     const int S = L.total, C = L.n_chains;
@@ -417,6 +426,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.exchange_every = cfg->exchange_every;
     T.spin_limit = 1u << 24;
     T.full_energy = (cfg->schedule & PT_SCHED_FULL_ENERGY) != 0 ? 1 : 0;
+    T.fp64_on_accept = (cfg->schedule & PT_SCHED_FP64_ON_ACCEPT) != 0 ? 1 : 0;
     T.seed = cfg->seed;
     T.k = k;
     h->d_tmp = (double *)(w + L.o_tmp);
@@ -495,7 +505,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     // once; the task flow for the others when their tasks are long (a sweep of
     // 1024 or more bead slots: shorter tasks pay more for their device-scope
     // fences and flags than one launch per sweep does); PT_SCHED_FLOW for all.
-    const int sched = cfg->schedule & ~PT_SCHED_FULL_ENERGY;
+    const int sched = cfg->schedule & ~kSchedFlags;
     if (sched != PT_SCHED_PER_SWEEP) {
         for (Class &cl : h->classes) {
             if (cl.lane) continue;
@@ -810,7 +820,7 @@ PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const do
     if (op < 0 || op > 8) return fail(PT_EINVAL, "unknown op %d", op);
     if ((op == 7 || op == 8) && n % 64 != 0) return fail(PT_EINVAL, "op %d needs n a multiple of 64", op);
     if (n == 0) return PT_OK;
-    const pt::Consts k = make_consts(model, true);
+    const pt::Consts k = make_consts(model, 0x1p-10);
     const size_t nin = (op == 6) ? 4 * (size_t)n : (size_t)n;
     const size_t ny = (op == 6) ? 2 : (size_t)n;
     const size_t nout = (op == 5) ? 2 * (size_t)n : (op == 6) ? 4 * (size_t)n : (size_t)n;
@@ -1085,7 +1095,7 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
     // class whose chains finish early only adds its time.  Moving a class into
     // a wider one that runs longer hides it, as long as the merged class still
     // fits on the device at once: greedy merges, timed on the whole batch.
-    if ((cfg->schedule & ~PT_SCHED_FULL_ENERGY) != PT_SCHED_PER_SWEEP) {
+    if ((cfg->schedule & ~kSchedFlags) != PT_SCHED_PER_SWEEP) {
         pt_config t = *cfg;
         t.series_capacity = 0;
         t.log_capacity = 0;

@@ -27,7 +27,7 @@ PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT, PT_SCHED_FLOW = 0, 1, 2,
 # The paper's alternative designs (see include/pt.h): or-ed into the schedule
 # (full energy after every sweep) or into a chain's mapping code (one lane per
 # replica, FP64 only).
-PT_SCHED_FULL_ENERGY, PT_MAP_LANE = 16, 0x100
+PT_SCHED_FULL_ENERGY, PT_SCHED_FP64_ON_ACCEPT, PT_MAP_LANE = 16, 32, 0x100
 PT_ENERGY_FP64_ORDER, PT_ENERGY_PAIR_PER_THREAD = 0, 1
 
 # Diagnostic ops of pt_selftest.

@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_1107_3490_amd import inputs as I
 
-from test_gpu_parity import _assert_same_state, _pt, assert_parity, run_both, run_gpu
+from test_gpu_parity import _assert_same_decisions, _assert_same_state, _pt, assert_parity, run_both, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -110,6 +110,23 @@ def test_full_energy_each_sweep_records_the_fp64_order_energy(variant):
     for key in ("coords", "energy", "alog", "elog"):
         assert np.array_equal(g[key], r[key]), key
     assert np.array_equal(g["obs"]["perm"], r["obs"]["perm"])
+
+
+@pytest.mark.parametrize("schedule", [1, 2, 3])
+def test_fp64_on_accept_gives_fp64_accurate_running_energies(schedule):
+    """Mixed precision with every accepted move re-scored in the FP64 order:
+    the oracle's decisions and state, the same decisions as plain mixed, and
+    running energies within 1e-9 of the FP64-order energy (the FP64 path's
+    bar); every accepted move counts as re-scored."""
+    pt = _pt()
+    w = I.make_workload([13, 100, 300], [6, 6, 4], [(0.2, 2.0)] * 3, "walk", 23, 0, "mixed")
+    sweeps = 10
+    print(f"\n[case] FP64 on accept, schedule {schedule}", flush=True)
+    g = run_gpu(w, sweeps, "mixed", schedule=schedule | pt.PT_SCHED_FP64_ON_ACCEPT)
+    assert_parity(g, _oracle(w, sweeps), "fp64")
+    counts = g["obs"]["counts"]
+    assert np.all(counts[:, 3] >= counts[:, 0])
+    _assert_same_decisions(g, run_gpu(w, sweeps, "mixed", schedule=schedule))
 
 
 def test_autotune_considers_one_lane_per_replica_for_fp64():

@@ -143,7 +143,9 @@ def test_ablation_flags_are_validated(L):
     cfg.mapping = None
     for sched, ok in ((pt.PT_SCHED_FULL_ENERGY, True), (pt.PT_SCHED_PER_SWEEP | pt.PT_SCHED_FULL_ENERGY, True),
                       (pt.PT_SCHED_PERSISTENT | pt.PT_SCHED_FULL_ENERGY, True), (pt.PT_SCHED_FLOW, True),
-                      (pt.PT_SCHED_FLOW | pt.PT_SCHED_FULL_ENERGY, True), (4, False), (32, False),
+                      (pt.PT_SCHED_FLOW | pt.PT_SCHED_FULL_ENERGY, True), (4, False), (64, False),
+                      (pt.PT_SCHED_FP64_ON_ACCEPT, True),
+                      (pt.PT_SCHED_FLOW | pt.PT_SCHED_FP64_ON_ACCEPT | pt.PT_SCHED_FULL_ENERGY, True),
                       (pt.PT_SCHED_FULL_ENERGY | 4, False), (-1, False)):
         cfg.schedule = sched
         n = L.pt_workspace_bytes(C.byref(m), C.byref(cfg))
