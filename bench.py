@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark: replica-exchange Metropolis sweeps of a bead-spring homopolymer
-on one MI355X, mixed precision (FP32 pair terms, FP64 sums and decisions)
-beside plain FP64, on the same seeded synthetic input.
+on one MI355X, mixed precision (FP32 Lennard-Jones terms and pair sums from
+FP64 separations; FP64 bond terms, energies and decisions) beside plain FP64,
+on the same seeded synthetic input.
 
 A step is one pass of the whole hot path over the batch: every slot does one
 sweep of N single-monomer moves (each scored against all N-1 other monomers
@@ -12,7 +13,9 @@ all replicas fit on the chip at once, one persistent launch runs all K steps;
 where they do not, one task-flow launch does.
 
 Prints one JSON line.  Default workload: one chain of N = 100 monomers,
-64 temperatures geometric in [0.1, 1.5], random-walk start, seed 2.
+64 temperatures geometric in [0.1, 1.5], random-walk start, seed 2; the line
+also holds sub-records of the two batched workloads (48 uneven chains; 16
+chains of N = 2000 with 256 slots each), each on its own step counts.
 """
 from __future__ import annotations
 
@@ -29,6 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 27          # two LJ evaluations (13 each) + their difference
+# Arithmetic of the mixed path (the `dtype` field): Lennard-Jones brackets in
+# FP32 from FP64 separations, summed in FP32; bond terms, running energies and
+# every decision in FP64; moves inside the guard band re-scored in FP64.
+MIXED_DTYPE = "f32 pair terms and pair sums, f64 separations, bonds, energies and decisions"
 PEAK_FP32 = 157.3e12        # MI355X FP32 vector, FLOP/s
 PEAK_FP64 = 78.6e12         # MI355X FP64 vector, FLOP/s
 
@@ -137,7 +144,7 @@ def cpu_baseline(w, budget_s=12.0, threads=None):
     sim.run(n)
     dt = time.perf_counter() - t0
     pairs = w.pair_interactions_per_sweep() * n
-    return dict(value=pairs / dt, unit="pair interactions/s", cores=threads, kind="oracle",
+    return dict(value=pairs / dt, unit="pair interactions/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
                 sample=f"{n} sweeps of the full workload ({pairs:.3e} pair interactions, "
                        f"{dt:.1f} s, OpenMP over slots, FP64 incl. per-sweep canonical energy)")
 
@@ -272,6 +279,85 @@ def ablations(sweeps=40, warmup=5):
             "energy_kernels": method_rows}
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def dominant_kernel(run):
+    """Name of the kernel that dominates the sweep time of a measured run: the
+    persistent launch of the widest class, else its task flow, else the
+    per-sweep kernel of the most expensive class."""
+    b_, w_ = max(run["classes"], key=lambda c: c[0] * c[1])
+    mode = run["class_mode"][(b_, w_)]
+    if mode == 1:
+        return f"k_run<{w_}, true>"
+    if mode == 2:
+        return f"k_flow<{b_}, {w_}, true>"
+    return f"k_sweep<{b_}, {w_}, true>"
+
+
+def roofline(w, run, steps, workload=None):
+    """Algorithmic FP32 FLOP/s of the sweep launches (27 per pair interaction)
+    over the average launch duration, against the FP32 vector peak."""
+    avg_kernel_s = run["sweep_kernel_ms"] / 1e3 / run["launches"]
+    flop_per_launch = FLOP_PER_PAIR * w.pair_interactions_per_sweep() * steps / run["launches"]
+    achieved = flop_per_launch / avg_kernel_s
+    kernel = dominant_kernel(run)
+    waves_of_n = {int(m[0]): int(m[2]) for m in run["mapping"]}
+    occupied = min(1024, sum(int(r) * waves_of_n[int(n)] for n, r in zip(w.n_beads, w.n_slots)))
+    traffic = measured_traffic(workload, kernel, steps / run["launches"]) if workload else None
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 FETCH_SIZE/WRITE_SIZE x copy calibration)",
+            "occupied_simds": occupied, "frac_of_occupied_simds": achieved / (PEAK_FP32 * occupied / 1024.0),
+            "avg_launch_ms": avg_kernel_s * 1e3, "flop_per_launch": flop_per_launch}
+
+
+def sub_record(name, steps, warmup, cpu_budget_s, with_cpu, cpu_chains=None):
+    """One of the batched workloads, both precisions on the same input, with its
+    own step counts (its first sweeps relax random-walk starts: the warm-up
+    keeps most of that out of the timed steps)."""
+    from paper_1107_3490_amd import inputs as I
+
+    w = I.named(name)
+    mixed = run_gpu(w, "mixed", steps, warmup)
+    fp64 = run_gpu(w, "fp64", steps, warmup)
+    pps = w.pair_interactions_per_sweep()
+    rec = {"workload": f"{name}: {WORKLOADS[name]}", "steps": steps, "warmup": warmup,
+           "pairs_per_step": pps, "slots": w.total_slots,
+           "mixed": {"value": mixed["pairs"] / (mixed["event_total_ms"] / 1e3), "unit": "pair interactions/s",
+                     "ms_per_step": mixed["event_total_ms"] / steps,
+                     "replica_sweeps_per_s": steps * w.total_slots / (mixed["event_total_ms"] / 1e3),
+                     "mapping_N_B_W": mixed["mapping"], "launches": mixed["launches"],
+                     "schedule": "+".join(sorted({("per-sweep", "persistent", "task flow")[m]
+                                                  for m in mixed["class_mode"].values()})),
+                     "rescored_moves": mixed["rescored"], "moves": mixed["moves"],
+                     "energy_resyncs": mixed["resyncs"], "exchange_fp64_recomputes": mixed["exch_recompute"],
+                     "roofline": roofline(w, mixed, steps, name)},
+           "fp64": {"value": fp64["pairs"] / (fp64["event_total_ms"] / 1e3), "unit": "pair interactions/s",
+                    "ms_per_step": fp64["event_total_ms"] / steps, "mapping_N_B_W": fp64["mapping"],
+                    "launches": fp64["launches"]}}
+    rec["mixed_over_fp64"] = rec["mixed"]["value"] / rec["fp64"]["value"]
+    if with_cpu:
+        ws = I.subset(w, cpu_chains) if cpu_chains is not None else w
+        cb = cpu_baseline(ws, budget_s=cpu_budget_s)
+        if cpu_chains is not None:
+            cb["sample"] = (f"extrapolated: chain(s) {list(cpu_chains)} of {w.n_chains} with all their slots "
+                            f"({cb['sample']}); the oracle's cost is linear in pair interactions, so its "
+                            "rate on the whole workload is this rate")
+            cb["extrapolated"] = True
+        rec["cpu_baseline"] = cb
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +365,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the sub-records of the batched workloads (c4, c5)")
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="0 auto, 1 one sweep launch per sweep, 2 persistent, 3 task flow")
     ap.add_argument("--no-tune", action="store_true", help="default mapping instead of the autotuner's")
@@ -321,21 +409,7 @@ def main():
     slots = w.total_slots
     value = mixed["pairs"] / (mixed["event_total_ms"] / 1e3)
     ms_per_step = mixed["event_total_ms"] / args.steps
-    # A persistent or task-flow launch covers all K sweeps (and their exchange
-    # steps); a per-sweep launch one sweep of one class.  Either way: algorithmic FLOPs
-    # of the timed sweeps over the summed launch time.
-    avg_kernel_s = mixed["sweep_kernel_ms"] / 1e3 / mixed["launches"]
-    flop_per_launch = FLOP_PER_PAIR * w.pair_interactions_per_sweep() * args.steps / mixed["launches"]
-    achieved = flop_per_launch / avg_kernel_s
     fp64_value = fp64["pairs"] / (fp64["event_total_ms"] / 1e3)
-    # The dominant kernel: the one class of the workload, or the most expensive one.
-    b_, w_ = max(mixed["classes"], key=lambda c: c[0] * c[1])
-    mode = mixed["class_mode"][(b_, w_)]
-    kernel = f"{('k_sweep', 'k_run', 'k_flow')[mode]}<{b_}, {w_}, true>"
-    # SIMDs a sweep can keep busy: one wavefront per SIMD at most for each of
-    # the W wavefronts of every replica (the latency-bound regime).
-    waves_of_n = {int(m[0]): int(m[2]) for m in mixed["mapping"]}
-    occupied = min(1024, sum(int(r) * waves_of_n[int(n)] for n, r in zip(w.n_beads, w.n_slots)))
     fp64_sweep_s = fp64["sweep_kernel_ms"] / 1e3 / args.steps
 
     out = {
@@ -349,7 +423,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair terms, f64 sums and decisions",
+        "dtype": MIXED_DTYPE,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "slots": slots, "n_beads": sorted(set(w.n_beads)),
@@ -377,26 +451,20 @@ def main():
             "fp64_flops_frac": FLOP_PER_PAIR * w.pair_interactions_per_sweep() / fp64_sweep_s / PEAK_FP64,
         },
         "mixed_over_fp64": value / fp64_value,
-        "roofline": {
-            "bound": "alu",
-            "kernel": kernel,
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP32 / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32,
-            "traffic": measured_traffic(args.workload, kernel, args.steps / mixed["launches"]),
-            "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 FETCH_SIZE/WRITE_SIZE x copy calibration)",
-            "occupied_simds": occupied,
-            "frac_of_occupied_simds": achieved / (PEAK_FP32 * occupied / 1024.0),
-            "avg_launch_ms": avg_kernel_s * 1e3,
-            "flop_per_launch": flop_per_launch,
-        },
+        "roofline": roofline(w, mixed, args.steps, args.workload),
     }
     out["incl_init_and_readback"] = with_transfers(w, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
         # one core, the convention of the paper's speed-ups (context only)
         out["cpu_baseline_1core"] = cpu_baseline(w, budget_s=5.0, threads=1)
+    if not args.no_batched and args.workload == "c2":
+        # The batched workloads the throughput targets are stated for, on their
+        # own step counts (see sub_record).
+        out["workloads"] = {
+            "c4": sub_record("c4", 500, 100, 10.0, not args.no_cpu),
+            "c5": sub_record("c5", 30, 30, 10.0, not args.no_cpu, cpu_chains=[0]),
+        }
     print(json.dumps(out), flush=True)
 
 

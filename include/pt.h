@@ -125,9 +125,12 @@ typedef struct pt_config {
 /* How pt_sweep runs a class of chains (chains with the same mapping).
  * PER_SWEEP: one sweep kernel launch per sweep, then an exchange kernel.
  * PERSISTENT: one launch for all n sweeps; every replica stays on the chip
- * and exchange attempts synchronise the two blocks of a pair only; used when
- * all replicas of the class fit on the device at once, else FLOW for classes
- * of 1024 or more bead slots per replica (64 W B), else PER_SWEEP.
+ * and exchange attempts synchronise the two blocks of a pair only.  The
+ * classes of one wavefront count W share that launch (each block runs its
+ * chain's bead count per lane) as long as all their replicas fit on the
+ * device at once; launches of different W follow one another.  A class that
+ * does not fit takes FLOW if it has 1024 or more bead slots per replica
+ * (64 W B), else PER_SWEEP.
  * FLOW: one launch for all n sweeps with as many blocks as fit; they take
  * (sweep, slot) tasks in order, each task sweeping one replica from device
  * memory, and the task that finishes an attempted pair's sweep second takes
@@ -239,12 +242,12 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
  * (their own slots, ladders, coordinates, precision and schedule) over
  * trial_sweeps sweeps after a warm-up, in a device workspace of its own on
  * hip_stream, and writes the fastest code to mapping_out[n_chains] (ready for
- * config.mapping).  Unless the schedule is
- * PT_SCHED_PER_SWEEP it then merges classes greedily -- all chains of one
- * mapping moved to a wider one that holds them -- while the whole batch,
- * timed the same way, gets at least 2% faster and every class still runs
- * persistently (persistent classes run one after another).  The caller's state is not
- * touched; results of a run do not depend on the mapping.  Synchronous.
+ * config.mapping).  Unless the schedule is PT_SCHED_PER_SWEEP it then times
+ * the whole batch on those choices and, for each wavefront count W, with
+ * every length on its fastest mapping of that W (persistent launches of
+ * different W run one after another), and keeps the fastest.  The caller's
+ * state is not touched; results of a run do not depend on the mapping.
+ * Synchronous.
  * Errors: as pt_init, and PT_ENOMEM when the device has no room. */
 PT_API int pt_autotune(const pt_model *model, const pt_config *config, int32_t trial_sweeps,
                        void *hip_stream, int32_t *mapping_out);
@@ -273,6 +276,15 @@ PT_API int pt_get_digests(pt_handle *h, uint64_t *h_digests);
 PT_API size_t pt_state_bytes(pt_handle *h);
 PT_API int pt_get_state(pt_handle *h, void *h_buf, size_t bytes);
 PT_API int pt_set_state(pt_handle *h, const void *h_buf, size_t bytes);
+
+/* Test hook: a factor >= 1 by which the guard bands of PT_MIXED are widened
+ * (the move band around the Metropolis threshold and, for both precisions,
+ * the band of the exchange test within which the FP64-order energies are
+ * recomputed; 1 by default).  A wider band sends more decisions to the FP64
+ * order without changing any of them, which exercises those paths.  Applies
+ * to later launches.  Errors: PT_EINVAL (NULL handle, factor < 1 or not
+ * finite). */
+PT_API int pt_set_guard_scale(pt_handle *h, double factor);
 
 /* Test hook: the number of polls (each a short sleep, about 2^24 by default:
  * seconds) after which a persistent or task-flow run's wait for an exchange

@@ -57,6 +57,7 @@ struct Tables {
     const int32_t *chain_slots;  // slots
     const int32_t *chain_slot0;  // first global slot
     const uint32_t *chain_sid;   // stream chain id (exchange counters)
+    const int32_t *chain_bpl;    // beads per lane of the chain's mapping
     // run state: te[0] = sweeps done (t), te[1] = exchange steps done (e)
     int64_t *te;
     // optional records
@@ -69,6 +70,7 @@ struct Tables {
     int32_t total_slots;
     int32_t exchange_every;
     uint32_t spin_limit;         // polls of a persistent run's partner wait before it gives up
+    double guard_scale;          // >= 1: widening of the guard bands (test hook; 1 by default)
     int32_t full_energy;         // nonzero: every sweep ends with the FP64-order energy
     int32_t fp64_on_accept;      // nonzero (mixed): accepted moves are re-scored in the FP64 order
     uint64_t seed;
@@ -92,17 +94,22 @@ hipError_t launch_energy_pairs(int bpl, int wpr, const Tables &T, const int32_t 
 hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *chain_list, int n_chains,
                            int max_pairs, int force, hipStream_t s);
 hipError_t launch_advance(const Tables &T, int force, hipStream_t s);
-// Persistent run of n_sweeps sweeps and exchange steps for one class (all of
-// its slots co-resident: cooperative launch).  *fits = 0 (and nothing is
-// launched) when the class does not fit on the device at once.
-hipError_t launch_run(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *conf_list,
-                      int n_items, int64_t n_sweeps, int64_t t0, int64_t e0, int *fits,
-                      hipStream_t s);
+// Persistent run of n_sweeps sweeps and exchange steps for the conformations
+// in conf_list (chains of one wavefront count wpr, any bead counts per lane up
+// to max_bpl).  Every block must be resident at once: the caller checks
+// n_items against run_capacity first.  Starts at the run counters in device
+// memory.  No device query: safe inside a graph capture.
+hipError_t run_capacity(int wpr, bool mixed, int max_bpl, int64_t *blocks);
+hipError_t launch_run(int wpr, bool mixed, const Tables &T, const int32_t *conf_list, int n_items,
+                      int max_bpl, int64_t n_sweeps, hipStream_t s);
 // Task flow of n_sweeps sweeps and exchange steps for one class whose slots do
-// not all fit on the device at once (any number of resident blocks).
+// not all fit on the device at once, on `resident` blocks (flow_capacity);
+// starts at the run counters in device memory.
+hipError_t flow_capacity(int bpl, int wpr, bool mixed, int64_t *blocks);
 hipError_t launch_flow(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *slot_list,
-                       int n_items, int64_t n_sweeps, int64_t t0, int64_t e0, hipStream_t s);
-hipError_t launch_set_te(const Tables &T, int64_t t, int64_t e, hipStream_t s);
+                       int n_items, int64_t n_sweeps, int64_t resident, hipStream_t s);
+// Run counters past n sweeps of persistent or task-flow launches.
+hipError_t launch_advance_n(const Tables &T, int64_t n, hipStream_t s);
 hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y,
                            double *out, int64_t n, hipStream_t s);
 

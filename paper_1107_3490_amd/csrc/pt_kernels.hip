@@ -444,7 +444,7 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 }
                 const double bs = K.kbound * bsum;
                 const double dem = K.four_eps * sm + df;  // bracket sum -> energy (Eq. 1)
-                const double bt = bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem);
+                const double bt = (bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem)) * T.guard_scale;
                 const double lo = dem - bt, hi = dem + bt;
                 // Straight-line: every outcome is computed, one is kept.
                 const bool sure_acc = (hi <= 0.0) | (beta * hi < th);
@@ -929,9 +929,9 @@ __device__ __forceinline__ bool exch_decide(const Tables &T, int c, int i, int64
     const U4 w = philox10(U4{(uint32_t)i, (uint32_t)e, T.chain_sid[c], 2u}, T.seed);
     const double pl = det_log(unit_open(w.x));
     const double dd = e1 - e2;
-    const double tot = (bb1 + bound_energy(T.k, log2c(n), n, e1, bb1) + bb2 +
-                        bound_energy(T.k, log2c(n), n, e2, bb2)) * (1.0 + 0x1p-20) +
-                       0x1p-50 * dabs(dd);
+    const double tot = ((bb1 + bound_energy(T.k, log2c(n), n, e1, bb1) + bb2 +
+                         bound_energy(T.k, log2c(n), n, e2, bb2)) * (1.0 + 0x1p-20) +
+                        0x1p-50 * dabs(dd)) * T.guard_scale;
     const double d1 = db * (dd - tot), d2 = db * (dd + tot);
     const double dlo = (d1 < d2) ? d1 : d2, dhi = (d1 < d2) ? d2 : d1;
     const bool sure_acc = (dlo >= 0.0) || (pl < dlo);
@@ -1025,26 +1025,23 @@ __device__ __forceinline__ bool wait_ge(const int64_t *p, int64_t v, int32_t *er
     return false;
 }
 
-// n_sweeps sweeps and exchange steps of every conformation in `list`, one
-// block per conformation, all blocks resident at once (cooperative launch).
-// A block keeps its replica in LDS and registers for the whole run and
-// follows it from slot to slot.  Exchange attempts synchronise pairs only:
-// after a sweep that is followed by an exchange step, the holder of slot g
-// publishes its running energy, coordinates and conformation id and sets
-// done[g] = t + 1; the holder of the lower slot of an attempted pair waits for
-// its partner's flag, decides exactly as k_exchange does, writes the new slot
-// assignment and sets dec[g+1] = t + 1, which the partner waits for.  Inside
-// the band the partner's FP64-order energy is computed from a copy of its
-// replica in the block's LDS, which is then refilled from the block's own
-// published copy.
+// n_sweeps sweeps and exchange steps of conformation q (one block of W
+// wavefronts), starting at sweep t0 and exchange step e0.  The block keeps
+// the replica in LDS and registers for the whole run and follows it from
+// slot to slot.  Exchange attempts synchronise pairs only: after a sweep that
+// is followed by an exchange step, the holder of slot g publishes its running
+// energy, coordinates and conformation id and sets done[g] = t + 1; the
+// holder of the lower slot of an attempted pair waits for its partner's flag,
+// decides exactly as k_exchange does, writes the new slot assignment and sets
+// dec[g+1] = t + 1, which the partner waits for.  Inside the band the
+// partner's FP64-order energy is computed from a copy of its replica in the
+// block's LDS, which is then refilled from the block's own published copy.
 template <int B, int W, bool MIXED>
-__global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *__restrict__ list,
-                                                int64_t n_sweeps, int64_t t0, int64_t e0) {
+__device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int32_t &s_slot, int32_t &s_ok,
+                                         const int q, const int64_t n_sweeps, const int64_t t0,
+                                         const int64_t e0) {
     using G = Geo<B, W>;
-    __shared__ SweepLds<B, W> S;
-    __shared__ int32_t s_slot, s_ok;
     const int tid = threadIdx.x;
-    const int q = list[blockIdx.x];
     const int c = T.slot_chain[q];
     const int n = T.chain_n[c];
     const int R = T.chain_slots[c];
@@ -1158,6 +1155,32 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
     copy_replica<B, W, G::NT>(cq, S.xyz);
 }
 
+// Dynamic LDS of the kernels whose blocks take different bead counts per
+// lane: each block views it as the SweepLds of its own B.
+extern __shared__ double pt_dyn_lds[];
+
+// Persistent run: n_sweeps sweeps and exchange steps of every conformation
+// in `list` (one block each, longest chains first), all blocks resident at
+// once (the host checks the occupancy before launching; an ordinary launch,
+// so it can be captured in a graph).  Chains of any bead count per lane B
+// share the launch: each block takes its chain's B from chain_bpl.  The run
+// starts at the device's run counters, which only a later kernel advances.
+template <int W, bool MIXED>
+__global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *__restrict__ list,
+                                                int64_t n_sweeps) {
+    __shared__ int32_t s_slot, s_ok;
+    const int q = list[blockIdx.x];
+    const int bpl = T.chain_bpl[T.slot_chain[q]];
+    const int64_t t0 = T.te[0], e0 = T.te[1];
+    switch (bpl) {
+        case 1: run_body<1, W, MIXED>(T, *reinterpret_cast<SweepLds<1, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
+        case 2: run_body<2, W, MIXED>(T, *reinterpret_cast<SweepLds<2, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
+        case 4: run_body<4, W, MIXED>(T, *reinterpret_cast<SweepLds<4, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
+        case 8: run_body<8, W, MIXED>(T, *reinterpret_cast<SweepLds<8, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
+        default: break;  // not a built class (the host never lists one)
+    }
+}
+
 // ------------------------------------------------------------- task flow --
 // n_sweeps sweeps and exchange steps of the S slots in `list` when they do not
 // all fit on the device at once: the resident blocks take tasks k = 0, 1, ...
@@ -1174,13 +1197,13 @@ __global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *_
 template <int B, int W, bool MIXED>
 __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Tables T,
                                                                        const int32_t *__restrict__ list,
-                                                                       int n_items, int64_t n_sweeps,
-                                                                       int64_t t0, int64_t e0) {
+                                                                       int n_items, int64_t n_sweeps) {
     using G = Geo<B, W>;
     __shared__ SweepLds<B, W> S;
     __shared__ int64_t s_task;
     __shared__ int32_t s_flag;
     const int tid = threadIdx.x;
+    const int64_t t0 = T.te[0], e0 = T.te[1];
     const int64_t total = n_sweeps * (int64_t)n_items;
     const int every = T.exchange_every;
     for (;;) {
@@ -1289,13 +1312,15 @@ __global__ void k_advance(const Tables T, int exchange_only) {
     if (due) T.te[1] += 1;
 }
 
-// Set the run counters (after persistent runs, whose kernels take them as
-// arguments).
-__global__ void k_set_te(const Tables T, int64_t t, int64_t e) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        T.te[0] = t;
-        T.te[1] = e;
-    }
+// Advance the run counters past n sweeps run by persistent or task-flow
+// launches (which read them at their start): t += n, and e by the exchange
+// steps due after sweeps t .. t + n - 1.
+__global__ void k_advance_n(const Tables T, int64_t n) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t t = T.te[0];
+    const int64_t ev = T.exchange_every;
+    T.te[0] = t + n;
+    if (ev > 0) T.te[1] += (t + n) / ev - t / ev;
 }
 
 // --------------------------------------------------------------- selftest --
@@ -1373,44 +1398,67 @@ hipError_t exchange_bw(const Tables &T, const int32_t *list, int nc, int mp, int
     return hipGetLastError();
 }
 
-template <int B, int W>
-hipError_t run_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64_t n_sweeps,
-                  int64_t t0, int64_t e0, int *fits, hipStream_t s) {
-    const void *f = mixed ? (const void *)k_run<B, W, true> : (const void *)k_run<B, W, false>;
-    int per_cu = 0, dev = 0, cus = 0, coop = 0;
+// LDS of a persistent block of bead count per lane bpl (dynamic: the blocks
+// of one launch view it as the SweepLds of their own B).
+template <int W>
+size_t run_lds(int bpl) {
+    switch (bpl) {
+        case 1: return sizeof(SweepLds<1, W>);
+        case 2: return sizeof(SweepLds<2, W>);
+        case 4: return sizeof(SweepLds<4, W>);
+        default: return sizeof(SweepLds<8, W>);
+    }
+}
+
+// Blocks of k_run<W> (with the LDS of bead count per lane max_bpl) that the
+// device holds at once.
+template <int W>
+hipError_t run_cap_w(bool mixed, int max_bpl, int64_t *blocks) {
+    const void *f = mixed ? (const void *)k_run<W, true> : (const void *)k_run<W, false>;
+    int per_cu = 0, dev = 0, cus = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (err == hipSuccess) err = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
-    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, 0);
-    if (err != hipSuccess) return err;
-    *fits = (coop != 0 && (int64_t)per_cu * cus >= n) ? 1 : 0;
-    if (!*fits || n <= 0 || n_sweeps <= 0) return hipSuccess;  // n_sweeps = 0: query only
-    Tables tt = T;
-    const int32_t *ll = list;
-    void *args[] = {(void *)&tt, (void *)&ll, (void *)&n_sweeps, (void *)&t0, (void *)&e0};
-    return hipLaunchCooperativeKernel(f, dim3(n), dim3(64 * W), args, 0, s);
+    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, run_lds<W>(max_bpl));
+    *blocks = (int64_t)per_cu * cus;
+    return err;
+}
+
+template <int W>
+hipError_t run_w(bool mixed, const Tables &T, const int32_t *list, int n, int max_bpl, int64_t n_sweeps,
+                 hipStream_t s) {
+    if (n <= 0 || n_sweeps <= 0) return hipSuccess;
+    const size_t lds = run_lds<W>(max_bpl);
+    if (mixed)
+        hipLaunchKernelGGL((k_run<W, true>), dim3(n), dim3(64 * W), lds, s, T, list, n_sweeps);
+    else
+        hipLaunchKernelGGL((k_run<W, false>), dim3(n), dim3(64 * W), lds, s, T, list, n_sweeps);
+    return hipGetLastError();
 }
 
 template <int B, int W>
-hipError_t flow_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64_t n_sweeps,
-                   int64_t t0, int64_t e0, hipStream_t s) {
+hipError_t flow_cap_bw(bool mixed, int64_t *blocks) {
     const void *f = mixed ? (const void *)k_flow<B, W, true> : (const void *)k_flow<B, W, false>;
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t err = hipGetDevice(&dev);
     if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, 0);
-    if (err != hipSuccess) return err;
+    *blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+    return err;
+}
+
+template <int B, int W>
+hipError_t flow_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64_t n_sweeps, int64_t resident,
+                   hipStream_t s) {
     if (n <= 0 || n_sweeps <= 0) return hipSuccess;
     const int64_t tasks = n_sweeps * (int64_t)n;
-    const int64_t resident = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
     const unsigned grid = (unsigned)(tasks < resident ? tasks : resident);
     hipLaunchKernelGGL(k_flow_reset, dim3(1), dim3(64), 0, s, T);
-    err = hipGetLastError();
+    hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (mixed)
-        hipLaunchKernelGGL((k_flow<B, W, true>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps, t0, e0);
+        hipLaunchKernelGGL((k_flow<B, W, true>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps);
     else
-        hipLaunchKernelGGL((k_flow<B, W, false>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps, t0, e0);
+        hipLaunchKernelGGL((k_flow<B, W, false>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps);
     return hipGetLastError();
 }
 
@@ -1474,16 +1522,34 @@ hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *lis
 #undef PT_EX
 }
 
-hipError_t launch_run(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
-                      int64_t n_sweeps, int64_t t0, int64_t e0, int *fits, hipStream_t s) {
-#define PT_RUN(B, W) run_bw<B, W>(mixed, T, list, n, n_sweeps, t0, e0, fits, s)
-    PT_DISPATCH(bpl, wpr, PT_RUN)
-#undef PT_RUN
+hipError_t run_capacity(int wpr, bool mixed, int max_bpl, int64_t *blocks) {
+    switch (wpr) {
+        case 1: return run_cap_w<1>(mixed, max_bpl, blocks);
+        case 2: return run_cap_w<2>(mixed, max_bpl, blocks);
+        case 4: return run_cap_w<4>(mixed, max_bpl, blocks);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_run(int wpr, bool mixed, const Tables &T, const int32_t *list, int n, int max_bpl,
+                      int64_t n_sweeps, hipStream_t s) {
+    switch (wpr) {
+        case 1: return run_w<1>(mixed, T, list, n, max_bpl, n_sweeps, s);
+        case 2: return run_w<2>(mixed, T, list, n, max_bpl, n_sweeps, s);
+        case 4: return run_w<4>(mixed, T, list, n, max_bpl, n_sweeps, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t flow_capacity(int bpl, int wpr, bool mixed, int64_t *blocks) {
+#define PT_FC(B, W) flow_cap_bw<B, W>(mixed, blocks)
+    PT_DISPATCH(bpl, wpr, PT_FC)
+#undef PT_FC
 }
 
 hipError_t launch_flow(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
-                       int64_t n_sweeps, int64_t t0, int64_t e0, hipStream_t s) {
-#define PT_FL(B, W) flow_bw<B, W>(mixed, T, list, n, n_sweeps, t0, e0, s)
+                       int64_t n_sweeps, int64_t resident, hipStream_t s) {
+#define PT_FL(B, W) flow_bw<B, W>(mixed, T, list, n, n_sweeps, resident, s)
     PT_DISPATCH(bpl, wpr, PT_FL)
 #undef PT_FL
 }
@@ -1493,8 +1559,8 @@ hipError_t launch_advance(const Tables &T, int exchange_only, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_set_te(const Tables &T, int64_t t, int64_t e, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_te, dim3(1), dim3(64), 0, s, T, t, e);
+hipError_t launch_advance_n(const Tables &T, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance_n, dim3(1), dim3(64), 0, s, T, n);
     return hipGetLastError();
 }
 

@@ -71,7 +71,7 @@ struct Layout {
     int64_t coord_total = 0, words_total = 0;
     size_t o_slot_chain, o_slot_index, o_slot_gid, o_beta, o_perm, o_acc, o_counts, o_word_off;
     size_t o_coord_off, o_e_run, o_b_run, o_coords, o_slot_of, o_done, o_dec, o_err;
-    size_t o_chain_n, o_chain_slots, o_chain_slot0, o_chain_sid;
+    size_t o_chain_n, o_chain_slots, o_chain_slot0, o_chain_sid, o_chain_bpl;
     size_t o_te, o_lists, o_tmp, o_alog, o_elog, o_series, o_dig;
     size_t o_flow_ready, o_flow_arr, o_flow_task;
     size_t bytes = 0;
@@ -192,8 +192,9 @@ Layout plan(const pt_config *c) {
     }
     L.log_cap = c->log_capacity;
     L.series_cap = c->series_capacity;
-    // lists: per class slot lists (total) + chain lists (n_chains)
-    L.lists_len = L.total + L.n_chains;
+    // lists: per class slot lists (total) + chain lists (n_chains) + the
+    // conformation lists of the persistent launches (total)
+    L.lists_len = 2 * L.total + L.n_chains;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     const size_t S = (size_t)L.total, C = (size_t)L.n_chains;
@@ -217,6 +218,7 @@ Layout plan(const pt_config *c) {
     L.o_chain_slots = take(4 * C);
     L.o_chain_slot0 = take(4 * C);
     L.o_chain_sid = take(4 * C);
+    L.o_chain_bpl = take(4 * C);
     L.o_te = take(16);
     L.o_dig = take(16 * S);
     L.o_flow_ready = take(8 * S);
@@ -245,12 +247,20 @@ double fene_y(const pt::Consts &k, const double *a, const double *b) {
 struct Class {
     int bpl = 0, wpr = 0;
     bool lane = false;        // one lane per replica (FP64 order, per-sweep launches)
-    bool persistent = false;  // whole sweeps run by one cooperative launch
+    bool persistent = false;  // whole sweeps run by a persistent launch (of its run group)
     bool flow = false;        // whole sweeps run by one task-flow launch (slots do not all fit)
     bool whole() const { return persistent || flow; }
     int n_slots = 0, n_chains = 0, max_pairs = 0;
     int32_t *d_slots = nullptr;   // slot (= starting conformation) list
     int32_t *d_chains = nullptr;  // chain list
+    int64_t resident = 0;         // task flow: blocks the device holds at once
+};
+
+// Persistent classes of one wavefront count W that run in one launch (every
+// block resident at once); blocks take their chain's B at run time.
+struct RunGroup {
+    int wpr = 0, max_bpl = 0, n = 0;
+    int32_t *d_list = nullptr;  // conformations, longest chains first
 };
 
 struct pt_handle {
@@ -263,10 +273,13 @@ struct pt_handle {
     char *ws = nullptr;
     bool mixed = false;
     std::vector<Class> classes;
+    std::vector<RunGroup> groups;
     std::vector<int32_t> n_beads, n_slots;
     int exchange_every = 1;
     int64_t t_host = 0, e_host = 0;  // counters as enqueued
     hipGraphExec_t graph1 = nullptr, graph16 = nullptr;
+    // Graphs of the persistent and task-flow launches of n sweeps, by n.
+    std::vector<std::pair<int64_t, hipGraphExec_t>> whole_graphs;
     double *d_tmp = nullptr;
     uint64_t seed = 0;
     bool failed = false;  // a persistent or task-flow run timed out; only pt_set_state recovers
@@ -407,6 +420,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.chain_slots = (const int32_t *)(w + L.o_chain_slots);
     T.chain_slot0 = (const int32_t *)(w + L.o_chain_slot0);
     T.chain_sid = (const uint32_t *)(w + L.o_chain_sid);
+    T.chain_bpl = (const int32_t *)(w + L.o_chain_bpl);
     T.te = (int64_t *)(w + L.o_te);
     T.slot_of = (int32_t *)(w + L.o_slot_of);
     T.done = (int64_t *)(w + L.o_done);
@@ -425,6 +439,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     T.total_slots = S;
     T.exchange_every = cfg->exchange_every;
     T.spin_limit = 1u << 24;
+    T.guard_scale = 1.0;
     T.full_energy = (cfg->schedule & PT_SCHED_FULL_ENERGY) != 0 ? 1 : 0;
     T.fp64_on_accept = (cfg->schedule & PT_SCHED_FP64_ON_ACCEPT) != 0 ? 1 : 0;
     T.seed = cfg->seed;
@@ -436,6 +451,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     for (int ch = 0; ch < C; ++ch) cls_chains[{L.bpl[ch], L.wpr[ch], (int)L.lane[ch]}].push_back(ch);
     std::vector<int32_t> lists;
     lists.reserve(L.lists_len);
+    std::vector<std::vector<int>> class_chains;
     for (auto &kv : cls_chains) {
         Class cl;
         cl.bpl = std::get<0>(kv.first);
@@ -454,13 +470,78 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
         cl.d_slots = (int32_t *)(w + L.o_lists) + slot_at;
         cl.d_chains = (int32_t *)(w + L.o_lists) + chain_at;
         h->classes.push_back(cl);
+        class_chains.push_back(kv.second);
     }
-
     auto fin = [&](int code) {
         if (code != PT_OK) pt_destroy(h);
         return code;
     };
+
+    // Persistent launches: the classes of one wavefront count W whose
+    // replicas fit on the device at once share one launch (a run group), the
+    // widest bead count per lane first, as long as the group still fits; a
+    // class that does not fit alone takes the task flow when its tasks are
+    // long (a sweep of 1024 or more bead slots: shorter tasks pay more for
+    // their device-scope fences and flags than one launch per sweep does),
+    // else one launch per sweep.  PT_SCHED_FLOW: the task flow for all.
+    const int sched = cfg->schedule & ~kSchedFlags;
+    if (sched != PT_SCHED_PER_SWEEP) {
+        std::vector<int> order;
+        for (int i = 0; i < (int)h->classes.size(); ++i)
+            if (!h->classes[i].lane) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const Class &x = h->classes[a], &y = h->classes[b];
+            return x.wpr != y.wpr ? x.wpr < y.wpr : x.bpl > y.bpl;
+        });
+        std::vector<char> placed(h->classes.size(), 0);
+        if (sched != PT_SCHED_FLOW) {
+            for (size_t a = 0; a < order.size(); ++a) {
+                const int lead = order[a];
+                if (placed[lead]) continue;
+                const Class &cl = h->classes[lead];
+                int64_t cap = 0;
+                hipError_t e0 = pt::run_capacity(cl.wpr, h->mixed, cl.bpl, &cap);
+                if (e0 != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e0)));
+                if (cl.n_slots > cap) continue;
+                std::vector<int> members = {lead};
+                int64_t count = cl.n_slots;
+                for (size_t b = a + 1; b < order.size(); ++b) {
+                    const Class &o = h->classes[order[b]];
+                    if (placed[order[b]] || o.wpr != cl.wpr || count + o.n_slots > cap) continue;
+                    members.push_back(order[b]);
+                    count += o.n_slots;
+                }
+                // Conformation q starts in slot q: the group's list holds the
+                // starting slots of its chains, longest chains first.
+                std::vector<int> chains;
+                for (int m : members) {
+                    placed[m] = 1;
+                    h->classes[m].persistent = true;
+                    chains.insert(chains.end(), class_chains[m].begin(), class_chains[m].end());
+                }
+                std::stable_sort(chains.begin(), chains.end(),
+                                 [&](int x, int y) { return cfg->n_beads[x] > cfg->n_beads[y]; });
+                RunGroup rg;
+                rg.wpr = cl.wpr;
+                rg.max_bpl = cl.bpl;
+                rg.n = (int)count;
+                rg.d_list = (int32_t *)(w + L.o_lists) + lists.size();
+                for (int ch : chains)
+                    for (int s = 0; s < cfg->n_slots[ch]; ++s) lists.push_back(chain_slot0[ch] + s);
+                h->groups.push_back(rg);
+            }
+        }
+        for (Class &cl : h->classes) {
+            cl.flow = !cl.lane && !cl.persistent && (sched == PT_SCHED_FLOW || 64 * cl.wpr * cl.bpl >= kFlowMinSlots);
+            if (cl.flow) {
+                hipError_t e0 = pt::flow_capacity(cl.bpl, cl.wpr, h->mixed, &cl.resident);
+                if (e0 != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e0)));
+            }
+        }
+    }
+
     std::vector<int64_t> te = {0, 0};
+    std::vector<int32_t> chain_bpl(L.bpl.begin(), L.bpl.end());
 #define PT_UP(off, vec) \
     if (!(vec).empty()) { \
         hipError_t e_ = hipMemcpyAsync(w + (off), (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice, h->stream); \
@@ -478,6 +559,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     PT_UP(L.o_chain_slots, chain_slots);
     PT_UP(L.o_chain_slot0, chain_slot0);
     PT_UP(L.o_chain_sid, chain_sid);
+    PT_UP(L.o_chain_bpl, chain_bpl);
     PT_UP(L.o_te, te);
     PT_UP(L.o_lists, lists);
     PT_UP(L.o_slot_of, perm);
@@ -501,47 +583,29 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     }
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "initialisation failed: %s", hipGetErrorString(e)));
-    // Persistent schedule for every class whose replicas fit on the device at
-    // once; the task flow for the others when their tasks are long (a sweep of
-    // 1024 or more bead slots: shorter tasks pay more for their device-scope
-    // fences and flags than one launch per sweep does); PT_SCHED_FLOW for all.
-    const int sched = cfg->schedule & ~kSchedFlags;
-    if (sched != PT_SCHED_PER_SWEEP) {
-        for (Class &cl : h->classes) {
-            if (cl.lane) continue;
-            if (sched != PT_SCHED_FLOW) {
-                int fits = 0;
-                e = pt::launch_run(cl.bpl, cl.wpr, h->mixed, T, cl.d_slots, cl.n_slots, 0, 0, 0, &fits, h->stream);
-                if (e != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e)));
-                cl.persistent = fits != 0;
-            }
-            cl.flow = !cl.persistent && (sched == PT_SCHED_FLOW || 64 * cl.wpr * cl.bpl >= kFlowMinSlots);
-        }
-    }
     e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return fin(fail(PT_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)));
     *out = h;
     return PT_OK;
 }
 
-// Persistent and task-flow classes: one launch each covers all n sweeps,
-// exchanges included.  With ev, brackets every launch with an event pair.
-int enqueue_persistent(pt_handle *h, int64_t n, std::vector<hipEvent_t> *ev, size_t *k) {
+// Persistent run groups and task-flow classes: one launch each covers all n
+// sweeps, exchanges included; they start at the device's run counters.  With
+// ev, brackets every launch with an event pair.
+int enqueue_persistent(pt_handle *h, int64_t n, hipStream_t s, std::vector<hipEvent_t> *ev, size_t *k) {
+    for (const RunGroup &g : h->groups) {
+        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k], s));
+        hipError_t e = pt::launch_run(g.wpr, h->mixed, h->T, g.d_list, g.n, g.max_bpl, n, s);
+        if (e != hipSuccess) return fail(PT_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
+        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k + 1], s));
+        if (k) ++*k;
+    }
     for (const Class &c : h->classes) {
-        if (!c.whole()) continue;
-        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k], h->stream));
-        if (c.persistent) {
-            int fits = 0;
-            hipError_t e = pt::launch_run(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, h->t_host,
-                                          h->e_host, &fits, h->stream);
-            if (e != hipSuccess) return fail(PT_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
-            if (!fits) return fail(PT_EHIP, "persistent class no longer fits on the device");
-        } else {
-            hipError_t e = pt::launch_flow(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, h->t_host,
-                                           h->e_host, h->stream);
-            if (e != hipSuccess) return fail(PT_EHIP, "task-flow launch failed: %s", hipGetErrorString(e));
-        }
-        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k + 1], h->stream));
+        if (!c.flow) continue;
+        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k], s));
+        hipError_t e = pt::launch_flow(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, n, c.resident, s);
+        if (e != hipSuccess) return fail(PT_EHIP, "task-flow launch failed: %s", hipGetErrorString(e));
+        if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k + 1], s));
         if (k) ++*k;
     }
     return PT_OK;
@@ -553,13 +617,71 @@ bool any_per_sweep(const pt_handle *h) {
     return false;
 }
 
+bool any_whole(const pt_handle *h) {
+    for (const Class &c : h->classes)
+        if (c.whole()) return true;
+    return false;
+}
+
+void drop_graphs(pt_handle *h) {
+    if (h->graph1) (void)hipGraphExecDestroy(h->graph1);
+    if (h->graph16) (void)hipGraphExecDestroy(h->graph16);
+    h->graph1 = h->graph16 = nullptr;
+    for (auto &x : h->whole_graphs) (void)hipGraphExecDestroy(x.second);
+    h->whole_graphs.clear();
+}
+
+// The graph of the persistent and task-flow launches of n sweeps (and of the
+// counter update when no class runs one launch per sweep), captured on first
+// use and kept for the last few sweep counts: every replay starts from the
+// run counters in device memory, so one graph serves every call with that n.
+int whole_graph(pt_handle *h, int64_t n, hipGraphExec_t *out) {
+    for (auto &x : h->whole_graphs)
+        if (x.first == n) {
+            *out = x.second;
+            return PT_OK;
+        }
+    hipGraph_t graph = nullptr;
+    PT_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_persistent(h, n, h->cap_stream, nullptr, nullptr);
+    if (rc == PT_OK && !any_per_sweep(h)) {
+        hipError_t e = pt::launch_advance_n(h->T, n, h->cap_stream);
+        if (e != hipSuccess) rc = fail(PT_EHIP, "counter update failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+    if (rc != PT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(PT_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    constexpr size_t kKeep = 4;
+    if (h->whole_graphs.size() >= kKeep) {
+        // The stream may still replay the oldest graph: destroy it after that.
+        PT_HIP(hipStreamSynchronize(h->stream));
+        (void)hipGraphExecDestroy(h->whole_graphs.front().second);
+        h->whole_graphs.erase(h->whole_graphs.begin());
+    }
+    h->whole_graphs.push_back({n, ex});
+    *out = ex;
+    return PT_OK;
+}
+
 PT_API int pt_sweep(pt_handle *h, int64_t n) {
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
     if (h->failed) return fail(PT_ESTATE, "the handle failed earlier; restore a state with pt_set_state");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
     if (n == 0) return PT_OK;
-    int rc = enqueue_persistent(h, n, nullptr, nullptr);
-    if (rc != PT_OK) return rc;
+    int rc = PT_OK;
+    if (any_whole(h)) {
+        hipGraphExec_t g = nullptr;
+        rc = whole_graph(h, n, &g);
+        if (rc != PT_OK) return rc;
+        PT_HIP(hipGraphLaunch(g, h->stream));
+    }
     if (any_per_sweep(h)) {
         if (n >= 16 && h->graph16 == nullptr) {
             rc = capture(h, 16, &h->graph16);
@@ -578,12 +700,8 @@ PT_API int pt_sweep(pt_handle *h, int64_t n) {
             PT_HIP(hipGraphLaunch(h->graph1, h->stream));
             left -= 1;
         }
-        advance_host(h, n);
-    } else {
-        advance_host(h, n);
-        hipError_t e = pt::launch_set_te(h->T, h->t_host, h->e_host, h->stream);
-        if (e != hipSuccess) return fail(PT_EHIP, "counter update failed: %s", hipGetErrorString(e));
     }
+    advance_host(h, n);
     return PT_OK;
 }
 
@@ -604,15 +722,18 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
     if (h == nullptr) return fail(PT_EINVAL, "NULL handle");
     if (h->failed) return fail(PT_ESTATE, "the handle failed earlier; restore a state with pt_set_state");
     if (n < 0) return fail(PT_EINVAL, "n_sweeps must be >= 0");
-    size_t per = 0, pers = 0;
-    for (const Class &c : h->classes) (c.whole() ? pers : per) += 1;
+    size_t per = 0, pers = h->groups.size();
+    for (const Class &c : h->classes) {
+        if (c.flow) pers += 1;
+        if (!c.whole()) per += 1;
+    }
     const size_t nev = pers + (size_t)n * per;
     std::vector<hipEvent_t> ev(2 * nev + 2, nullptr);
     for (auto &x : ev) PT_HIP(hipEventCreate(&x));
     int rc = PT_OK;
     PT_HIP(hipEventRecord(ev[2 * nev], h->stream));
     size_t k = 0;
-    if (n > 0) rc = enqueue_persistent(h, n, &ev, &k);
+    if (n > 0) rc = enqueue_persistent(h, n, h->stream, &ev, &k);
     for (int64_t i = 0; i < n && rc == PT_OK && per > 0; ++i) {
         for (const Class &c : h->classes) {
             if (c.whole()) continue;
@@ -633,11 +754,11 @@ PT_API int pt_time_sweeps(pt_handle *h, int64_t n, double *sweep_ms, double *tot
         }
     }
     if (rc == PT_OK && n > 0) {
-        advance_host(h, n);
         if (per == 0) {
-            hipError_t e = pt::launch_set_te(h->T, h->t_host, h->e_host, h->stream);
+            hipError_t e = pt::launch_advance_n(h->T, n, h->stream);
             if (e != hipSuccess) rc = fail(PT_EHIP, "counter update failed: %s", hipGetErrorString(e));
         }
+        advance_host(h, n);
     }
     PT_HIP(hipEventRecord(ev[2 * nev + 1], h->stream));
     PT_HIP(hipEventSynchronize(ev[2 * nev + 1]));
@@ -846,8 +967,10 @@ PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const do
 
 PT_API void pt_destroy(pt_handle *h) {
     if (h == nullptr) return;
-    if (h->graph1) (void)hipGraphExecDestroy(h->graph1);
-    if (h->graph16) (void)hipGraphExecDestroy(h->graph16);
+    // Work enqueued on the caller's stream may still replay the handle's
+    // graphs: wait for it before they go.
+    (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }
@@ -1027,6 +1150,7 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
     }
     std::map<int, std::vector<int>> by_n;
     for (int c = 0; c < C; ++c) by_n[cfg->n_beads[c]].push_back(c);
+    std::map<int, std::vector<std::pair<int, double>>> timed;  // length -> (code, ms)
     for (auto &kv : by_n) {
         const int n = kv.first;
         const std::vector<int> &chains = kv.second;
@@ -1083,6 +1207,7 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
                 if (h) pt_destroy(h);
                 (void)hipFree(ws);
                 if (rc != PT_OK) return rc;
+                timed[n].push_back({code, ms});
                 if (best == 0 || ms < best_ms) {
                     best = code;
                     best_ms = ms;
@@ -1091,72 +1216,85 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
         }
         for (int c : chains) out[c] = best;
     }
-    // Persistent classes run one after another, each for all sweeps, so a
-    // class whose chains finish early only adds its time.  Moving a class into
-    // a wider one that runs longer hides it, as long as the merged class still
-    // fits on the device at once: greedy merges, timed on the whole batch.
+    // Persistent classes of one wavefront count share a launch, but launches
+    // of different wavefront counts run one after another, so a batch split
+    // over several counts adds their times.  Candidates for the whole batch:
+    // the per-length choices above, and for each wavefront count W every
+    // length on its fastest timed mapping with W (or the smallest bead count
+    // that holds it at W); the fastest batch wins.
     if ((cfg->schedule & ~kSchedFlags) != PT_SCHED_PER_SWEEP) {
         pt_config t = *cfg;
         t.series_capacity = 0;
         t.log_capacity = 0;
-        std::vector<int32_t> mp(out, out + C);
-        // Whole-batch time of a mapping; *ok = every chain runs persistently.
-        auto time_batch = [&](const std::vector<int32_t> &m, double *ms, bool *ok) -> int {
+        auto time_batch = [&](const std::vector<int32_t> &m, double *ms) -> int {
             t.mapping = m.data();
             const size_t bytes = plan(&t).bytes;
             void *ws = nullptr;
             if (hipMalloc(&ws, bytes) != hipSuccess) return fail(PT_ENOMEM, "autotune: no room for %zu bytes", bytes);
             pt_handle *h = nullptr;
             int r = pt_init(model, &t, ws, bytes, hip_stream, &h);
-            *ok = r == PT_OK;
-            for (int c = 0; r == PT_OK && c < C; ++c) *ok = *ok && h->L.bpl[c] == ((m[c] >> 4) & 15);
-            if (r == PT_OK)
-                for (const Class &cl : h->classes) *ok = *ok && cl.persistent;
             if (r == PT_OK) r = pt_sweep(h, std::min<int64_t>(trial_sweeps, 4));
             if (r == PT_OK) r = pt_time_sweeps(h, trial_sweeps, nullptr, ms, nullptr);
             if (h) pt_destroy(h);
             (void)hipFree(ws);
             return r;
         };
-        double cur_ms = 0.0;
-        bool ok = false;
-        rc = time_batch(mp, &cur_ms, &ok);
-        if (rc != PT_OK) return rc;
-        for (int round = 0; ok && round < 8; ++round) {
-            std::map<int, int> max_n;  // code -> longest chain in that class
-            for (int c = 0; c < C; ++c) max_n[mp[c]] = std::max(max_n[mp[c]], cfg->n_beads[c]);
-            if (max_n.size() < 2) break;
-            std::vector<int32_t> best_mp;
-            double best_ms = cur_ms * 0.98;  // a merge must gain at least 2%
-            for (auto &x : max_n)
-                for (auto &y : max_n) {
-                    const int cy = y.first;
-                    if (x.first == cy || ((x.first | cy) & PT_MAP_LANE) != 0 ||
-                        64 * (cy & 15) * ((cy >> 4) & 15) < x.second)
-                        continue;
-                    std::vector<int32_t> cand = mp;
-                    for (int c = 0; c < C; ++c)
-                        if (cand[c] == x.first) cand[c] = cy;
-                    double ms = 0.0;
-                    bool fits = false;
-                    rc = time_batch(cand, &ms, &fits);
-                    if (rc != PT_OK) return rc;
-                    if (fits && ms < best_ms) {
-                        best_ms = ms;
-                        best_mp = cand;
+        std::vector<std::vector<int32_t>> cands = {std::vector<int32_t>(out, out + C)};
+        for (int W : {1, 2, 4}) {
+            std::vector<int32_t> m(C, 0);
+            bool ok = true, differs = false;
+            for (int c = 0; c < C && ok; ++c) {
+                const int n = cfg->n_beads[c];
+                int code = 0;
+                double best_ms = 0.0;
+                for (const auto &x : timed[n])
+                    if ((x.first & PT_MAP_LANE) == 0 && (x.first & 15) == W && (code == 0 || x.second < best_ms)) {
+                        code = x.first;
+                        best_ms = x.second;
                     }
+                if (code == 0) {
+                    int b = 1;
+                    while (b < 8 && 64 * W * b < n) b <<= 1;
+                    if (64 * W * b < n) ok = false;
+                    code = 16 * b + W;
                 }
-            if (best_mp.empty()) break;
-            mp = best_mp;
-            cur_ms = best_ms;
+                m[c] = code;
+                differs = differs || code != out[c];
+            }
+            if (ok && differs) cands.push_back(m);
         }
-        std::copy(mp.begin(), mp.end(), out);
+        if (cands.size() > 1) {
+            size_t best = 0;
+            double best_ms = 0.0;
+            for (size_t i = 0; i < cands.size(); ++i) {
+                double ms = 0.0;
+                rc = time_batch(cands[i], &ms);
+                if (rc != PT_OK) return rc;
+                if (i == 0 || ms < best_ms) {
+                    best = i;
+                    best_ms = ms;
+                }
+            }
+            std::copy(cands[best].begin(), cands[best].end(), out);
+        }
     }
     return PT_OK;
 }
 
 PT_API int pt_set_spin_limit(pt_handle *h, uint32_t polls) {
     if (h == nullptr || polls < 1) return fail(PT_EINVAL, "NULL handle or zero polls");
+    // Graphs hold the kernel arguments of their capture: capture them anew.
+    PT_HIP(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
     h->T.spin_limit = polls;
+    return PT_OK;
+}
+
+PT_API int pt_set_guard_scale(pt_handle *h, double factor) {
+    if (h == nullptr || !(isfinite(factor) && factor >= 1.0))
+        return fail(PT_EINVAL, "NULL handle, or a guard scale that is not a finite number >= 1");
+    PT_HIP(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->T.guard_scale = factor;
     return PT_OK;
 }

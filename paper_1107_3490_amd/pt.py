@@ -37,7 +37,7 @@ EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_autotune", "pt_sweep", "pt_excha
            "pt_energy_method",
            "pt_observables", "pt_reset_observables", "pt_get_coords", "pt_get_running",
            "pt_get_series", "pt_get_logs", "pt_get_digests", "pt_state_bytes", "pt_get_state",
-           "pt_set_state", "pt_set_spin_limit", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
+           "pt_set_state", "pt_set_spin_limit", "pt_set_guard_scale", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
            "pt_last_error")
 
 
@@ -94,6 +94,7 @@ def lib():
         L.pt_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.pt_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.pt_set_spin_limit.argtypes = [C.c_void_p, C.c_uint32]
+        L.pt_set_guard_scale.argtypes = [C.c_void_p, C.c_double]
         L.pt_selftest.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), C.c_int64]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_destroy.restype = None
@@ -396,3 +397,8 @@ class Simulation:
     def set_spin_limit(self, polls: int) -> None:
         """Test hook for the bounded waits of the persistent and task-flow schedules."""
         _check(lib().pt_set_spin_limit(C.c_void_p(self.h), int(polls)))
+
+    def set_guard_scale(self, factor: float) -> None:
+        """Test hook: widen the guard bands by factor >= 1 (decisions unchanged;
+        more of them go to the FP64 order)."""
+        _check(lib().pt_set_guard_scale(C.c_void_p(self.h), float(factor)))
