@@ -1,4 +1,7 @@
-"""Build the CPU oracle (test infrastructure) into oracle/liboracle.so with gcc."""
+"""Build the CPU oracle (test infrastructure) into oracle/liboracle.so with gcc.
+
+build(sanitize=True, out=...) builds an AddressSanitizer + UndefinedBehavior-
+Sanitizer copy (for the sanitized run of the oracle's pin tests)."""
 from __future__ import annotations
 
 import os
@@ -15,14 +18,19 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"
           "-fno-fast-math", "-fno-math-errno", "-Wall", "-Wextra"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]
+# Sanitized build: every undefined-behaviour report is fatal.
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = None) -> str:
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = ["gcc", *CFLAGS, *(SANITIZE if sanitize else []), SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# PT_ORACLE_LIB selects another build of the same source (the sanitized one).
+LIB_PATH = os.environ.get("PT_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 _lib = None
 

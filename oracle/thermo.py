@@ -6,8 +6,14 @@ Per slot (one temperature each), over the sweeps after a burn-in fraction:
   <E>, <R_gyr^2>, <R_ee^2>        plain means (Eqs. 7-8),
   C_V/N = beta^2 (<E^2> - <E>^2) / N   specific heat per monomer (Sec. 4,
                                        k_B = 1),
+  d<R_gyr^2>/dT = beta^2 (<R_gyr^2 E> - <R_gyr^2><E>)
+                                       the temperature derivative of the
+                                       canonical mean of R_gyr^2 (k_B = 1),
+                                       the reading taken of the paper's
+                                       "fluctuation of r_gyr^2" (Sec. 4.1),
 with errors from M equal consecutive bins: the standard error of the bin
-means for the plain averages, the jackknife over the same bins for C_V/N.
+means for the plain averages, the jackknife over the same bins for C_V/N and
+d<R_gyr^2>/dT.
 Written as plain loops so that it can be read against these definitions.
 """
 import math
@@ -45,6 +51,25 @@ def specific_heat(es, beta, n_beads, m=32):
     return cv, err
 
 
+def rg2_temperature_derivative(rgs, es, beta, m=32):
+    """d<R_gyr^2>/dT and its jackknife error over m bins.  In the canonical
+    ensemble <A> = sum A exp(-beta E) / Z, so d<A>/dbeta = -(<A E> - <A><E>)
+    and, with beta = 1/T, d<A>/dT = beta^2 (<A E> - <A><E>)."""
+    sa, size = _bin_sums(rgs, m)
+    se, _ = _bin_sums(es, m)
+    sae, _ = _bin_sums([a * e for a, e in zip(rgs, es)], m)
+    ta, te, tae, cnt = sum(sa), sum(se), sum(sae), size * m
+    d = beta * beta * (tae / cnt - (ta / cnt) * (te / cnt))
+    loo = []
+    for b in range(m):
+        k = cnt - size
+        a1, e1, ae1 = (ta - sa[b]) / k, (te - se[b]) / k, (tae - sae[b]) / k
+        loo.append(beta * beta * (ae1 - a1 * e1))
+    lbar = sum(loo) / m
+    err = math.sqrt((m - 1) / m * sum((c - lbar) ** 2 for c in loo))
+    return d, err
+
+
 def estimates(series, betas, n_beads, burn_in=0.2, m=32):
     """series: [sweeps][slots][3] of (E, R_ee^2, R_gyr^2); betas and n_beads
     per slot.  Returns a list of dicts, one per slot."""
@@ -59,5 +84,7 @@ def estimates(series, betas, n_beads, burn_in=0.2, m=32):
         cv, dcv = specific_heat(es, float(betas[g]), int(n_beads[g]), m)
         r2, dr2 = mean_and_error(rg, m)
         q2, dq2 = mean_and_error(ree, m)
-        out.append(dict(E=e, dE=de, Cv=cv, dCv=dcv, Rg2=r2, dRg2=dr2, Ree2=q2, dRee2=dq2))
+        dt, ddt = rg2_temperature_derivative(rg, es, float(betas[g]), m)
+        out.append(dict(E=e, dE=de, Cv=cv, dCv=dcv, Rg2=r2, dRg2=dr2, Ree2=q2, dRee2=dq2,
+                        dRg2dT=dt, ddRg2dT=ddt))
     return out

@@ -18,7 +18,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpt.so")
-SOURCES = [os.path.join(CSRC, "pt_kernels.hip"), os.path.join(CSRC, "pt_runtime.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("pt_k_run1m.hip", "pt_k_run2m.hip", "pt_k_run4m.hip", "pt_k_run1d.hip", "pt_k_run2d.hip",
+            "pt_k_run4d.hip", "pt_k_flow.hip", "pt_k_sweep.hip", "pt_k_misc.hip", "pt_k_run.hip",
+            "pt_runtime.cpp")]
 ARCH = "gfx950"
 
 
@@ -33,22 +36,30 @@ def flags():
             "-I", INCLUDE, "-I", CSRC]
 
 
+def _compile(src, extra, verbose):
+    obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+    lang = ["-x", "hip"] if src.endswith(".cpp") else []
+    cmd = [hipcc(), *flags(), *extra, *lang, "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{out}")
+    if verbose and out.strip():
+        print(out)
+    return obj
+
+
 def build(verbose: bool = False, extra=()) -> str:
+    """Compiles the translation units in parallel (one hipcc each) and links
+    them into libpt.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     tmp = LIB + ".tmp"
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc(), *flags(), *extra, *lang, "-c", src, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-        out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{out}")
-        if verbose and out.strip():
-            print(out)
-        objs.append(obj)
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda src: _compile(src, extra, verbose), SOURCES))
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -97,11 +97,12 @@ hipError_t launch_advance(const Tables &T, int force, hipStream_t s);
 // Persistent run of n_sweeps sweeps and exchange steps for the conformations
 // in conf_list (chains of one wavefront count wpr, any bead counts per lane up
 // to max_bpl).  Every block must be resident at once: the caller checks
-// n_items against run_capacity first.  Starts at the run counters in device
-// memory.  No device query: safe inside a graph capture.
-hipError_t run_capacity(int wpr, bool mixed, int max_bpl, int64_t *blocks);
-hipError_t launch_run(int wpr, bool mixed, const Tables &T, const int32_t *conf_list, int n_items,
-                      int max_bpl, int64_t n_sweeps, hipStream_t s);
+// n_items against run_capacity first.  dense selects the build whose
+// registers leave room for more blocks per compute unit.  Starts at the run
+// counters in device memory.  No device query: safe inside a graph capture.
+hipError_t run_capacity(int wpr, bool mixed, int max_bpl, bool dense, int64_t *blocks);
+hipError_t launch_run(int wpr, bool mixed, bool dense, const Tables &T, const int32_t *conf_list,
+                      int n_items, int max_bpl, int64_t n_sweeps, hipStream_t s);
 // Task flow of n_sweeps sweeps and exchange steps for one class whose slots do
 // not all fit on the device at once, on `resident` blocks (flow_capacity);
 // starts at the run counters in device memory.

@@ -1,7 +1,10 @@
-// pt_kernels.hip -- gfx950 kernels of libpt.so: Metropolis sweeps of single-
-// monomer moves, the FP64-order energy, and neighbour-temperature replica
-// exchange for a bead-spring homopolymer (Gross, Janke, Bachmann,
-// arXiv:1107.3490, Secs. 3.1-3.4).
+// pt_kernels.hpp -- device code of the gfx950 kernels of libpt.so: Metropolis
+// sweeps of single-monomer moves, the FP64-order energy, and neighbour-
+// temperature replica exchange for a bead-spring homopolymer (Gross, Janke,
+// Bachmann, arXiv:1107.3490, Secs. 3.1-3.4).  Included by the translation
+// units that instantiate and launch the kernels (pt_k_*.hip), so that they
+// compile in parallel; everything here has internal linkage.
+#pragma once
 //
 // Mapping.  A replica is owned by W wavefronts (W = 1, 2 or 4; 64 W lanes),
 // each lane holding the contiguous bead block [t B, (t+1) B) of the padded
@@ -1165,9 +1168,11 @@ extern __shared__ double pt_dyn_lds[];
 // so it can be captured in a graph).  Chains of any bead count per lane B
 // share the launch: each block takes its chain's B from chain_bpl.  The run
 // starts at the device's run counters, which only a later kernel advances.
-template <int W, bool MIXED>
-__global__ __launch_bounds__(64 * W) void k_run(const Tables T, const int32_t *__restrict__ list,
-                                                int64_t n_sweeps) {
+// MINW is the minimum number of wavefronts per SIMD the registers must allow:
+// 1 for batches that fit anyway (no spills), more for dense batches.
+template <int W, bool MIXED, int MINW>
+__global__ __launch_bounds__(64 * W, MINW) void k_run(const Tables T, const int32_t *__restrict__ list,
+                                                      int64_t n_sweeps) {
     __shared__ int32_t s_slot, s_ok;
     const int q = list[blockIdx.x];
     const int bpl = T.chain_bpl[T.slot_chain[q]];
@@ -1293,111 +1298,6 @@ __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Ta
     }
 }
 
-// Reset of the task counter of k_flow (a kernel, not a memset: safe to capture).
-__global__ void k_flow_reset(const Tables T) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *T.flow_task = 0;
-}
-
-// Advance the run counters after a sweep (t += 1, and e += 1 when an exchange
-// step was due) or after an explicit exchange step (e += 1 only).
-__global__ void k_advance(const Tables T, int exchange_only) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int64_t t = T.te[0];
-    if (exchange_only) {
-        T.te[1] += 1;
-        return;
-    }
-    const bool due = T.exchange_every > 0 && (t + 1) % T.exchange_every == 0;
-    T.te[0] = t + 1;
-    if (due) T.te[1] += 1;
-}
-
-// Advance the run counters past n sweeps run by persistent or task-flow
-// launches (which read them at their start): t += n, and e by the exchange
-// steps due after sweeps t .. t + n - 1.
-__global__ void k_advance_n(const Tables T, int64_t n) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int64_t t = T.te[0];
-    const int64_t ev = T.exchange_every;
-    T.te[0] = t + n;
-    if (ev > 0) T.te[1] += (t + n) / ev - t / ev;
-}
-
-// --------------------------------------------------------------- selftest --
-__global__ void k_selftest(const Consts k, int op, const double *x, const double *y, double *out,
-                           int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (op == 7 || op == 8) {
-        // Whole wavefronts: n is a multiple of 64 (checked by the host).
-        if (i - (int64_t)(threadIdx.x & 63) >= n) return;
-        out[i] = (op == 7) ? wave_tree(x[i]) : (double)wave_tree((float)x[i]);
-        return;
-    }
-    if (i >= n) return;
-    switch (op) {
-        case 0: out[i] = __builtin_sqrt(x[i]); break;
-        case 1: out[i] = x[i] / y[i]; break;
-        case 2: out[i] = det_log(x[i]); break;
-        case 3: out[i] = fene64(k, x[i]); break;
-        case 4: out[i] = lj64(k, x[i]); break;
-        case 5: {
-            // One pair whose old separation lies on the cutoff, as the sweep
-            // scores it: 4 eps (g(r) - g(rc)) and its bound.
-            const Lj32 r = lj32(k, sq3(x[i], y[i], 0.0));
-            const Lj32 c = lj32(k, k.rc2);
-            out[2 * i] = k.four_eps * (double)(r.g - c.g);
-            const float sb = r.s6 + c.s6;
-            out[2 * i + 1] = k.kbound * (double)__builtin_fmaf(sb, sb, sb);
-            break;
-        }
-        case 6: {
-            const uint64_t seed = ((uint64_t)(uint32_t)y[1] << 32) | (uint64_t)(uint32_t)y[0];
-            const U4 w = philox10(U4{(uint32_t)x[4 * i], (uint32_t)x[4 * i + 1],
-                                     (uint32_t)x[4 * i + 2], (uint32_t)x[4 * i + 3]}, seed);
-            out[4 * i] = w.x;
-            out[4 * i + 1] = w.y;
-            out[4 * i + 2] = w.z;
-            out[4 * i + 3] = w.w;
-            break;
-        }
-        default: break;
-    }
-}
-
-template <int B, int W>
-hipError_t sweep_bw(bool mixed, const Tables &T, const int32_t *list, int n, hipStream_t s) {
-    if (mixed)
-        hipLaunchKernelGGL((k_sweep<B, W, true>), dim3(n), dim3(64 * W), 0, s, T, list);
-    else
-        hipLaunchKernelGGL((k_sweep<B, W, false>), dim3(n), dim3(64 * W), 0, s, T, list);
-    return hipGetLastError();
-}
-
-template <int B, int W>
-hipError_t sweep_lane_bw(const Tables &T, const int32_t *list, int n, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep_lane<B, W>), dim3((n + 63) / 64), dim3(64), 0, s, T, list, n);
-    return hipGetLastError();
-}
-
-template <int B, int W>
-hipError_t energy_bw(const Tables &T, const int32_t *list, int n, double *oe, double *ob, int by_slot,
-                     hipStream_t s) {
-    hipLaunchKernelGGL((k_energy<B, W>), dim3(n), dim3(64 * W), 0, s, T, list, oe, ob, by_slot);
-    return hipGetLastError();
-}
-
-template <int B, int W>
-hipError_t energy_pairs_bw(const Tables &T, const int32_t *list, int n, double *oe, double *ob, hipStream_t s) {
-    hipLaunchKernelGGL((k_energy_pairs<B, W>), dim3(n), dim3(64 * W), 0, s, T, list, oe, ob);
-    return hipGetLastError();
-}
-
-template <int B, int W>
-hipError_t exchange_bw(const Tables &T, const int32_t *list, int nc, int mp, int force, hipStream_t s) {
-    hipLaunchKernelGGL((k_exchange<B, W>), dim3(nc * mp), dim3(64 * W), 0, s, T, list, mp, force);
-    return hipGetLastError();
-}
-
 // LDS of a persistent block of bead count per lane bpl (dynamic: the blocks
 // of one launch view it as the SweepLds of their own B).
 template <int W>
@@ -1408,58 +1308,6 @@ size_t run_lds(int bpl) {
         case 4: return sizeof(SweepLds<4, W>);
         default: return sizeof(SweepLds<8, W>);
     }
-}
-
-// Blocks of k_run<W> (with the LDS of bead count per lane max_bpl) that the
-// device holds at once.
-template <int W>
-hipError_t run_cap_w(bool mixed, int max_bpl, int64_t *blocks) {
-    const void *f = mixed ? (const void *)k_run<W, true> : (const void *)k_run<W, false>;
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t err = hipGetDevice(&dev);
-    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, run_lds<W>(max_bpl));
-    *blocks = (int64_t)per_cu * cus;
-    return err;
-}
-
-template <int W>
-hipError_t run_w(bool mixed, const Tables &T, const int32_t *list, int n, int max_bpl, int64_t n_sweeps,
-                 hipStream_t s) {
-    if (n <= 0 || n_sweeps <= 0) return hipSuccess;
-    const size_t lds = run_lds<W>(max_bpl);
-    if (mixed)
-        hipLaunchKernelGGL((k_run<W, true>), dim3(n), dim3(64 * W), lds, s, T, list, n_sweeps);
-    else
-        hipLaunchKernelGGL((k_run<W, false>), dim3(n), dim3(64 * W), lds, s, T, list, n_sweeps);
-    return hipGetLastError();
-}
-
-template <int B, int W>
-hipError_t flow_cap_bw(bool mixed, int64_t *blocks) {
-    const void *f = mixed ? (const void *)k_flow<B, W, true> : (const void *)k_flow<B, W, false>;
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t err = hipGetDevice(&dev);
-    if (err == hipSuccess) err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * W, 0);
-    *blocks = (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
-    return err;
-}
-
-template <int B, int W>
-hipError_t flow_bw(bool mixed, const Tables &T, const int32_t *list, int n, int64_t n_sweeps, int64_t resident,
-                   hipStream_t s) {
-    if (n <= 0 || n_sweeps <= 0) return hipSuccess;
-    const int64_t tasks = n_sweeps * (int64_t)n;
-    const unsigned grid = (unsigned)(tasks < resident ? tasks : resident);
-    hipLaunchKernelGGL(k_flow_reset, dim3(1), dim3(64), 0, s, T);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    if (mixed)
-        hipLaunchKernelGGL((k_flow<B, W, true>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps);
-    else
-        hipLaunchKernelGGL((k_flow<B, W, false>), dim3(grid), dim3(64 * W), 0, s, T, list, n, n_sweeps);
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -1481,95 +1329,5 @@ hipError_t flow_bw(bool mixed, const Tables &T, const int32_t *list, int n, int6
         case 8 * 16 + 4: return CALL(8, 4);   \
         default: return hipErrorInvalidValue; \
     }
-
-hipError_t launch_sweep(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
-                        hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-#define PT_SW(B, W) sweep_bw<B, W>(mixed, T, list, n, s)
-    PT_DISPATCH(bpl, wpr, PT_SW)
-#undef PT_SW
-}
-
-hipError_t launch_sweep_lane(int bpl, int wpr, const Tables &T, const int32_t *list, int n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-#define PT_SL(B, W) sweep_lane_bw<B, W>(T, list, n, s)
-    PT_DISPATCH(bpl, wpr, PT_SL)
-#undef PT_SL
-}
-
-hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *list, int n, double *out_e,
-                         double *out_b, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int by_slot = (out_b == nullptr) ? 1 : 0;
-#define PT_EN(B, W) energy_bw<B, W>(T, list, n, out_e, out_b, by_slot, s)
-    PT_DISPATCH(bpl, wpr, PT_EN)
-#undef PT_EN
-}
-
-hipError_t launch_energy_pairs(int bpl, int wpr, const Tables &T, const int32_t *list, int n, double *out_e,
-                               double *out_b, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-#define PT_EP(B, W) energy_pairs_bw<B, W>(T, list, n, out_e, out_b, s)
-    PT_DISPATCH(bpl, wpr, PT_EP)
-#undef PT_EP
-}
-
-hipError_t launch_exchange(int bpl, int wpr, const Tables &T, const int32_t *list, int n_chains,
-                           int max_pairs, int force, hipStream_t s) {
-    if (n_chains <= 0 || max_pairs <= 0) return hipSuccess;
-#define PT_EX(B, W) exchange_bw<B, W>(T, list, n_chains, max_pairs, force, s)
-    PT_DISPATCH(bpl, wpr, PT_EX)
-#undef PT_EX
-}
-
-hipError_t run_capacity(int wpr, bool mixed, int max_bpl, int64_t *blocks) {
-    switch (wpr) {
-        case 1: return run_cap_w<1>(mixed, max_bpl, blocks);
-        case 2: return run_cap_w<2>(mixed, max_bpl, blocks);
-        case 4: return run_cap_w<4>(mixed, max_bpl, blocks);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_run(int wpr, bool mixed, const Tables &T, const int32_t *list, int n, int max_bpl,
-                      int64_t n_sweeps, hipStream_t s) {
-    switch (wpr) {
-        case 1: return run_w<1>(mixed, T, list, n, max_bpl, n_sweeps, s);
-        case 2: return run_w<2>(mixed, T, list, n, max_bpl, n_sweeps, s);
-        case 4: return run_w<4>(mixed, T, list, n, max_bpl, n_sweeps, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t flow_capacity(int bpl, int wpr, bool mixed, int64_t *blocks) {
-#define PT_FC(B, W) flow_cap_bw<B, W>(mixed, blocks)
-    PT_DISPATCH(bpl, wpr, PT_FC)
-#undef PT_FC
-}
-
-hipError_t launch_flow(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *list, int n,
-                       int64_t n_sweeps, int64_t resident, hipStream_t s) {
-#define PT_FL(B, W) flow_bw<B, W>(mixed, T, list, n, n_sweeps, resident, s)
-    PT_DISPATCH(bpl, wpr, PT_FL)
-#undef PT_FL
-}
-
-hipError_t launch_advance(const Tables &T, int exchange_only, hipStream_t s) {
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, T, exchange_only);
-    return hipGetLastError();
-}
-
-hipError_t launch_advance_n(const Tables &T, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_advance_n, dim3(1), dim3(64), 0, s, T, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y, double *out,
-                           int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_selftest, dim3((unsigned)blocks), dim3(256), 0, s, k, op, x, y, out, n);
-    return hipGetLastError();
-}
 
 }  // namespace pt

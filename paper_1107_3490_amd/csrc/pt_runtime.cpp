@@ -260,6 +260,7 @@ struct Class {
 // block resident at once); blocks take their chain's B at run time.
 struct RunGroup {
     int wpr = 0, max_bpl = 0, n = 0;
+    bool dense = false;         // the register-capped build (more blocks per compute unit)
     int32_t *d_list = nullptr;  // conformations, longest chains first
 };
 
@@ -499,9 +500,13 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
                 const int lead = order[a];
                 if (placed[lead]) continue;
                 const Class &cl = h->classes[lead];
-                int64_t cap = 0;
-                hipError_t e0 = pt::run_capacity(cl.wpr, h->mixed, cl.bpl, &cap);
+                // The build without a register cap when the group fits with it,
+                // else the capped one with room for more blocks.
+                int64_t cap_free = 0, cap = 0;
+                hipError_t e0 = pt::run_capacity(cl.wpr, h->mixed, cl.bpl, false, &cap_free);
+                if (e0 == hipSuccess) e0 = pt::run_capacity(cl.wpr, h->mixed, cl.bpl, true, &cap);
                 if (e0 != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e0)));
+                cap = std::max(cap, cap_free);
                 if (cl.n_slots > cap) continue;
                 std::vector<int> members = {lead};
                 int64_t count = cl.n_slots;
@@ -525,6 +530,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
                 rg.wpr = cl.wpr;
                 rg.max_bpl = cl.bpl;
                 rg.n = (int)count;
+                rg.dense = count > cap_free;
                 rg.d_list = (int32_t *)(w + L.o_lists) + lists.size();
                 for (int ch : chains)
                     for (int s = 0; s < cfg->n_slots[ch]; ++s) lists.push_back(chain_slot0[ch] + s);
@@ -595,7 +601,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
 int enqueue_persistent(pt_handle *h, int64_t n, hipStream_t s, std::vector<hipEvent_t> *ev, size_t *k) {
     for (const RunGroup &g : h->groups) {
         if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k], s));
-        hipError_t e = pt::launch_run(g.wpr, h->mixed, h->T, g.d_list, g.n, g.max_bpl, n, s);
+        hipError_t e = pt::launch_run(g.wpr, h->mixed, g.dense, h->T, g.d_list, g.n, g.max_bpl, n, s);
         if (e != hipSuccess) return fail(PT_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
         if (ev) PT_HIP(hipEventRecord((*ev)[2 * *k + 1], s));
         if (k) ++*k;

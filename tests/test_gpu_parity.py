@@ -323,10 +323,10 @@ def test_flow_runs_classes_that_do_not_fit():
 
 
 def test_thermodynamics_agree_with_oracle():
-    """Per-temperature <E> and C_V/N of the mixed GPU run (from its running
-    energies) lie within 2 sigma of the oracle's estimates, sigma being the
-    oracle's binned / jackknife error, on the full small-chain run; the device
-    accumulators agree with the series."""
+    """Per-temperature <E>, C_V/N, <R_gyr^2> and d<R_gyr^2>/dT of the mixed GPU
+    run (from its running energies) lie within 2 sigma of the oracle's
+    estimates, sigma being the oracle's binned / jackknife error, on the full
+    small-chain run; the device accumulators agree with the series."""
     from oracle import thermo as OT
     from paper_1107_3490_amd import thermo as TH
     pt = _pt()
@@ -345,6 +345,9 @@ def test_thermodynamics_agree_with_oracle():
         assert abs(p["E"][g] - o[g]["E"]) <= 2 * o[g]["dE"], (g, p["E"][g], o[g])
         assert abs(p["Cv"][g] - o[g]["Cv"]) <= 2 * o[g]["dCv"], (g, p["Cv"][g], o[g])
         assert abs(p["Rg2"][g] - o[g]["Rg2"]) <= 2 * o[g]["dRg2"], (g, p["Rg2"][g], o[g])
+        # d<R_gyr^2>/dT (the paper's fluctuation of r_gyr^2, Eq. 8): the
+        # package's estimate against the oracle's plain-loop estimator
+        assert abs(p["dRg2dT"][g] - o[g]["dRg2dT"]) <= 2 * o[g]["ddRg2dT"], (g, p["dRg2dT"][g], o[g])
     a = TH.from_accumulators(acc, w.betas, nb)
     whole = TH.estimates(ser, w.betas, nb, burn_in=0.0, n_bins=25)
     assert np.all(a["n"] == w.sweeps)

@@ -66,7 +66,7 @@ def test_package_estimates_match_oracle_estimates():
     o = OT.estimates(s, betas, nb, burn_in=0.2, m=32)
     p = PT.estimates(s, betas, nb, burn_in=0.2, n_bins=32)
     for g in range(slots):
-        for k in ("E", "dE", "Cv", "dCv", "Rg2", "dRg2", "Ree2", "dRee2"):
+        for k in ("E", "dE", "Cv", "dCv", "Rg2", "dRg2", "Ree2", "dRee2", "dRg2dT", "ddRg2dT"):
             assert abs(p[k][g] - o[g][k]) <= 1e-9 * max(1.0, abs(o[g][k])), (g, k, p[k][g], o[g][k])
 
 
@@ -82,3 +82,35 @@ def test_accumulator_summary_matches_series_means():
     p = PT.estimates(s, [1.0, 2.0, 3.0], [10, 10, 10], burn_in=0.0, n_bins=10)
     for k in ("E", "Cv", "Rg2", "Ree2"):
         assert np.allclose(a[k], p[k], rtol=1e-12, atol=0)
+
+
+def test_oracle_rg2_derivative_bivariate_normal_closed_form():
+    """d<R_gyr^2>/dT = beta^2 Cov(R_gyr^2, E).  For jointly normal (R_gyr^2, E)
+    with standard deviations s_a, s_e and correlation rho the covariance is
+    rho s_a s_e, and the sample covariance of n independent draws has the
+    standard error sqrt((s_a^2 s_e^2 + (rho s_a s_e)^2) / n) (Isserlis'
+    theorem for the fourth moment of normals)."""
+    n, beta = 64000, 1.3
+    s_a, s_e = 0.8, 2.5
+    for rho in (0.6, -0.35, 0.0):
+        rng = np.random.default_rng(int(100 + 100 * rho))
+        z1, z2 = rng.standard_normal(n), rng.standard_normal(n)
+        a = 3.0 + s_a * z1
+        e = -40.0 + s_e * (rho * z1 + math.sqrt(1 - rho * rho) * z2)
+        d, err = OT.rg2_temperature_derivative(list(a), list(e), beta, m=32)
+        cov = rho * s_a * s_e
+        se = beta * beta * math.sqrt((s_a * s_a * s_e * s_e + cov * cov) / n)
+        assert abs(d - beta * beta * cov) < 3.5 * se, (rho, d, beta * beta * cov, se)
+        assert 0.7 < err / se < 1.3, (rho, err, se)
+
+
+def test_oracle_rg2_derivative_of_a_function_of_energy():
+    """If R_gyr^2 = c E + k exactly, the covariance is c Var(E): the estimate
+    is beta^2 c times the (biased, 1/n) sample variance of E, to rounding."""
+    rng = np.random.default_rng(9)
+    es = list(-20 + 1.5 * rng.standard_normal(32 * 100))
+    c, k, beta = -0.25, 7.0, 0.9
+    d, _ = OT.rg2_temperature_derivative([c * x + k for x in es], es, beta, m=32)
+    mu = sum(es) / len(es)
+    var = sum((x - mu) ** 2 for x in es) / len(es)
+    assert abs(d - beta * beta * c * var) <= 1e-9 * abs(beta * beta * c * var)
