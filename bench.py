@@ -85,11 +85,14 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
 
 
 def kernel_sources_sha256():
+    """SHA-256 over every device source of the library (kernels, device
+    helpers, the persistent and task-flow instantiations), in name order."""
+    csrc = os.path.join(ROOT, "paper_1107_3490_amd", "csrc")
     h = hashlib.sha256()
-    for fn in ("paper_1107_3490_amd/csrc/pt_kernels.hip", "paper_1107_3490_amd/csrc/pt_device.hpp",
-               "paper_1107_3490_amd/csrc/pt_internal.hpp"):
-        with open(os.path.join(ROOT, fn), "rb") as f:
-            h.update(f.read())
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".hpp", ".inc")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
