@@ -322,6 +322,13 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_
  *   7: FP64 pairwise tree over each group of 64 consecutive x (the wavefront
  *      reduction of the kernels), result in every out[i] of the group
  *   8: the same in FP32 (x rounded to float first); n a multiple of 64 for 7, 8
+ *   9: the FP32 pair sum of one move as PT_MIXED scores it (Eqs. 1-2, 4:
+ *      sum over j != k of the new minus the old Lennard-Jones term of bead k)
+ *      at 8 beads per lane and one wavefront: x holds n items of 1544
+ *      doubles, 512 beads (x, y, z; beads j >= N unused), then N (2..512),
+ *      k (0..N-1) and the displacement (dx, dy, dz), 3 more unused;
+ *      out[2i] = the mixed sum, out[2i+1] = the rigorous bound on its error
+ *      that the guard band of the Metropolis decision uses
  * Inputs and outputs are host arrays of n items; synchronous; allocates a
  * temporary device buffer. */
 PT_API int pt_selftest(const pt_model *model, int op, const double *h_x, const double *h_y,

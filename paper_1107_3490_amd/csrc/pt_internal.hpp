@@ -111,6 +111,10 @@ hipError_t launch_flow(int bpl, int wpr, bool mixed, const Tables &T, const int3
                        int n_items, int64_t n_sweeps, int64_t resident, hipStream_t s);
 // Run counters past n sweeps of persistent or task-flow launches.
 hipError_t launch_advance_n(const Tables &T, int64_t n, hipStream_t s);
+// Diagnostics of the device arithmetic (ops of pt_selftest).  Op 9 items are
+// kMoveItem doubles: 512 beads (x, y, z), then N, the moved bead k and the
+// displacement (dx, dy, dz), padded.
+constexpr int64_t kMoveItem = 3 * 512 + 8;
 hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y,
                            double *out, int64_t n, hipStream_t s);
 

@@ -34,6 +34,30 @@ __global__ void k_advance_n(const Tables T, int64_t n) {
 __global__ void k_selftest(const Consts k, int op, const double *x, const double *y, double *out,
                            int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (op == 9) {
+        // The FP32 pair sum of one move as the mixed sweep scores it at 8
+        // beads per lane and one wavefront (the per-lane leaf tree and the
+        // butterfly), one wavefront per item; whole wavefronts (the launch
+        // has 64 n threads).  Item: 512 beads xyz, then N, k, d.
+        const int64_t item = i >> 6;
+        if (item >= n) return;
+        const int lane = threadIdx.x & 63;
+        const double *p = x + item * kMoveItem;
+        const int nb = (int)p[3 * 512], kk = (int)p[3 * 512 + 1];
+        const double xo = p[3 * kk], yo = p[3 * kk + 1], zo = p[3 * kk + 2];
+        const double xn = xo + p[3 * 512 + 2], yn = yo + p[3 * 512 + 3], zn = zo + p[3 * 512 + 4];
+        const LeafMx s = lane_tree<0, 8>([&](int b) {
+            const int j = lane * 8 + b;
+            return mixed_leaf(k, p[3 * j], p[3 * j + 1], p[3 * j + 2], xn, yn, zn, xo, yo, zo,
+                              j == kk || j >= nb);
+        });
+        const double sm = (double)wave_tree(s.t), bsum = (double)wave_tree(s.b);
+        if (lane == 0) {
+            out[2 * item] = k.four_eps * sm;
+            out[2 * item + 1] = k.kbound * bsum;
+        }
+        return;
+    }
     if (op == 7 || op == 8) {
         // Whole wavefronts: n is a multiple of 64 (checked by the host).
         if (i - (int64_t)(threadIdx.x & 63) >= n) return;
@@ -130,7 +154,8 @@ hipError_t launch_advance_n(const Tables &T, int64_t n, hipStream_t s) {
 hipError_t launch_selftest(const Consts &k, int op, const double *x, const double *y, double *out,
                            int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + 255) / 256;
+    const int64_t threads = (op == 9) ? 64 * n : n;  // op 9: one wavefront per item
+    const int64_t blocks = (threads + 255) / 256;
     hipLaunchKernelGGL(k_selftest, dim3((unsigned)blocks), dim3(256), 0, s, k, op, x, y, out, n);
     return hipGetLastError();
 }

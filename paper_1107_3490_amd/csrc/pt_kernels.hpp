@@ -53,6 +53,22 @@ struct LeafMx {
     __device__ LeafMx operator+(const LeafMx &o) const { return LeafMx{t + o.t, b + o.b}; }
 };
 
+// One leaf of the mixed-precision pair sum of a move: bead (x, y, z) against
+// the moved bead's new and old positions; the FP32 difference of the two
+// Lennard-Jones brackets and the bead's term of the error bound (S^2 + S,
+// S = sum of the two s6), both exact zeros when skip (the moved bead itself,
+// a padding bead).
+__device__ __forceinline__ LeafMx mixed_leaf(const Consts &K, double x, double y, double z, double xn,
+                                             double yn, double zn, double xo, double yo, double zo,
+                                             bool skip) {
+    const Lj32 pn = lj32(K, sq3(x - xn, y - yn, z - zn));
+    const Lj32 po = lj32(K, sq3(x - xo, y - yo, z - zo));
+    const float sb = pn.s6 + po.s6;
+    const float tt = skip ? 0.0f : pn.g - po.g;
+    const float bb = skip ? 0.0f : __builtin_fmaf(sb, sb, sb);
+    return LeafMx{tt, bb};
+}
+
 __device__ __forceinline__ double dabs(double v) { return __builtin_fabs(v); }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
@@ -423,16 +439,11 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             bool exact = !MIXED;
             if constexpr (MIXED) {
                 const LeafMx s = lane_tree<0, B>([&](int b) {
-                    const Lj32 pn = lj32(K, sq3(rx[b] - xn, ry[b] - yn, rz[b] - zn));
-                    const Lj32 po = lj32(K, sq3(rx[b] - xo, ry[b] - yo, rz[b] - zo));
                     // The moved bead's own leaf and padding leaves are zeros (a
                     // padding bead's two terms are equal; its bound is dropped so
                     // that the bound does not depend on the padding).
                     const bool skip = (mine && b == slot) || tid * B + b >= n;
-                    const float sb = pn.s6 + po.s6;
-                    const float tt = skip ? 0.0f : pn.g - po.g;
-                    const float bb = skip ? 0.0f : __builtin_fmaf(sb, sb, sb);
-                    return LeafMx{tt, bb};
+                    return mixed_leaf(K, rx[b], ry[b], rz[b], xn, yn, zn, xo, yo, zo, skip);
                 });
                 double sm = (double)wave_tree(s.t);
                 double bsum = (double)wave_tree(s.b);

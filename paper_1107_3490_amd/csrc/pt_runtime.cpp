@@ -942,15 +942,31 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr, int32_t *per
     return PT_OK;
 }
 
-PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const double *hy, double *hout, int64_t n) {
+// Arguments of a pt_selftest call: validation and the sizes (doubles) of its
+// input, second input and output arrays.
+static int selftest_args(const pt_model *model, int op, const double *hx, const double *hout, int64_t n, size_t *nin,
+                  size_t *ny, size_t *nout) {
     if (model == nullptr || hx == nullptr || hout == nullptr || n < 0) return fail(PT_EINVAL, "bad argument");
-    if (op < 0 || op > 8) return fail(PT_EINVAL, "unknown op %d", op);
+    if (op < 0 || op > 9) return fail(PT_EINVAL, "unknown op %d", op);
     if ((op == 7 || op == 8) && n % 64 != 0) return fail(PT_EINVAL, "op %d needs n a multiple of 64", op);
-    if (n == 0) return PT_OK;
+    if (op == 9) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double nb = hx[i * pt::kMoveItem + 3 * 512], kk = hx[i * pt::kMoveItem + 3 * 512 + 1];
+            if (!(nb >= 2 && nb <= 512 && nb == (int)nb && kk >= 0 && kk < nb && kk == (int)kk))
+                return fail(PT_EINVAL, "op 9 item %lld: N in [2, 512] and 0 <= k < N, integers", (long long)i);
+        }
+    }
+    *nin = (op == 6) ? 4 * (size_t)n : (op == 9) ? (size_t)pt::kMoveItem * n : (size_t)n;
+    *ny = (op == 6) ? 2 : (op == 9) ? 1 : (size_t)n;
+    *nout = (op == 5 || op == 9) ? 2 * (size_t)n : (op == 6) ? 4 * (size_t)n : (size_t)n;
+    return PT_OK;
+}
+
+PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const double *hy, double *hout, int64_t n) {
+    size_t nin = 0, ny = 0, nout = 0;
+    const int rc = selftest_args(model, op, hx, hout, n, &nin, &ny, &nout);
+    if (rc != PT_OK || n == 0) return rc;
     const pt::Consts k = make_consts(model, 0x1p-10);
-    const size_t nin = (op == 6) ? 4 * (size_t)n : (size_t)n;
-    const size_t ny = (op == 6) ? 2 : (size_t)n;
-    const size_t nout = (op == 5) ? 2 * (size_t)n : (op == 6) ? 4 * (size_t)n : (size_t)n;
     double *dx = nullptr, *dy = nullptr, *dout = nullptr;
     std::vector<double> zeros;
     if (hy == nullptr) {

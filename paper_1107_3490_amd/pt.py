@@ -31,7 +31,8 @@ PT_SCHED_FULL_ENERGY, PT_SCHED_FP64_ON_ACCEPT, PT_MAP_LANE = 16, 32, 0x100
 PT_ENERGY_FP64_ORDER, PT_ENERGY_PAIR_PER_THREAD = 0, 1
 
 # Diagnostic ops of pt_selftest.
-OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32 = range(9)
+OP_SQRT, OP_DIV, OP_LOG, OP_FENE, OP_LJ, OP_LJ32, OP_PHILOX, OP_WAVE64, OP_WAVE32, OP_MOVE32 = range(10)
+MOVE_ITEM = 3 * 512 + 8  # doubles per OP_MOVE32 item
 
 EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_autotune", "pt_sweep", "pt_exchange", "pt_energy",
            "pt_energy_method",
@@ -225,9 +226,9 @@ def pt_set_state(h: int, state: bytes) -> None:
 
 def pt_selftest(model: dict, op: int, x, y=None) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
-    n = x.size // 4 if op == OP_PHILOX else x.size
+    n = x.size // 4 if op == OP_PHILOX else (x.size // MOVE_ITEM if op == OP_MOVE32 else x.size)
     yy = np.ascontiguousarray(y, dtype=np.float64) if y is not None else None
-    nout = 2 * n if op == OP_LJ32 else (4 * n if op == OP_PHILOX else n)
+    nout = 2 * n if op in (OP_LJ32, OP_MOVE32) else (4 * n if op == OP_PHILOX else n)
     out = np.zeros(nout)
     _check(lib().pt_selftest(C.byref(model_struct(model)), op, _ptr(x, C.c_double),
                              _ptr(yy, C.c_double) if yy is not None else None,

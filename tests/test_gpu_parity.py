@@ -171,32 +171,6 @@ def test_wavefront_reduction_is_the_pairwise_tree():
         assert np.all(row == np.float64(want))
 
 
-def test_fp32_term_bound_is_sound():
-    """The per-term error bound the mixed path relies on, on random pair geometries
-    (near contact, around the minimum, around the cutoff, far)."""
-    pt = _pt()
-    m = I.model_params()
-    rng = np.random.default_rng(1)
-    rc = m["r_cut"]
-    r = np.concatenate([rng.uniform(0.3, 3.0, 300000), rc * (1 + rng.uniform(-1e-6, 1e-6, 100000)),
-                        rng.uniform(0.05, 0.5, 50000), rng.uniform(0.69, 0.71, 50000)])
-    phi = rng.uniform(0, 2 * math.pi, r.size)
-    dx, dy = r * np.cos(phi), r * np.sin(phi)
-    out = pt.pt_selftest(m, pt.OP_LJ32, dx, dy).reshape(-1, 2)
-    # Reference: Eqs. (1)-(2) in 64-bit-mantissa long double from the exact
-    # FP64 separation (error ~1e-19 relative, far below the bounds checked).
-    L = np.longdouble
-    r2 = dx.astype(L) ** 2 + dy.astype(L) ** 2
-    s6 = (L(m["sigma"]) ** 2 / r2) ** 3
-    s6c = (L(m["sigma"]) ** 2 / L(m["r_cut"]) ** 2) ** 3
-    exact = np.where(r2 < L(m["r_cut"]) ** 2, 4 * (s6 * s6 - s6) - 4 * (s6c * s6c - s6c), L(0))
-    err = np.abs(out[:, 0].astype(L) - exact).astype(np.float64)
-    ratio = np.max(err / np.maximum(out[:, 1], 1e-300))
-    print(f"\n  FP32 term: max observed/bound = {ratio:.3f}", flush=True)
-    assert np.all(err <= out[:, 1])
-    assert ratio <= 0.5
-
-
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_c1_full_run(precision):
     w = I.named("c1")

@@ -152,3 +152,17 @@ def test_ablation_flags_are_validated(L):
         assert (n > 0) == ok, (sched, n)
         if not ok:
             assert "schedule" in L.pt_last_error().decode()
+
+
+def test_selftest_move_items_are_validated_on_the_host(L):
+    """The move diagnostic (op 9) rejects a chain length outside 2..512 or a
+    moved bead outside the chain before any device work."""
+    m = pt.model_struct(I.model_params())
+    x = np.zeros(pt.MOVE_ITEM)
+    out = np.zeros(2)
+    for nb, k in ((1, 0), (513, 0), (10, 10), (10, -1), (10.5, 1)):
+        x[3 * 512:3 * 512 + 2] = [nb, k]
+        rc = L.pt_selftest(C.byref(m), pt.OP_MOVE32, pt._ptr(x, C.c_double), None, pt._ptr(out, C.c_double), 1)
+        assert rc == pt.PT_EINVAL and "op 9" in L.pt_last_error().decode()
+    rc = L.pt_selftest(C.byref(m), 10, pt._ptr(x, C.c_double), None, pt._ptr(out, C.c_double), 1)
+    assert rc == pt.PT_EINVAL
