@@ -334,6 +334,22 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *beads_per_lane, int32_t *waves_
 PT_API int pt_selftest(const pt_model *model, int op, const double *h_x, const double *h_y,
                        double *h_out, int64_t n);
 
+/* For callers that cannot allocate device memory (code running while a HIP
+ * graph is being captured around it, tight serving loops, harnesses that
+ * forbid hipMalloc): pt_selftest with the same ops, arguments, results and
+ * errors, whose device staging (inputs, second input, outputs) lives in a
+ * fixed device array of 2^21 doubles (16 MiB) per GPU, held from the first
+ * call on that GPU until the process ends, instead of buffers allocated per
+ * call.  Calls no hipMalloc or hipFree.  A call needing more staging than the
+ * array holds (n items need n + n + n doubles for ops 0-4, 7 and 8 -- the
+ * second input only for op 1 --, 4n + 2 + 4n for op 6, 2n + 2n for op 5 and
+ * 1544 n + 2 n for op 9) fails with PT_EINVAL before any device work.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several host threads) race and must be serialised by the caller.
+ * Synchronous, on the null stream of the current device. */
+PT_API int pt_selftest_noalloc(const pt_model *model, int op, const double *h_x, const double *h_y,
+                               double *h_out, int64_t n);
+
 PT_API void pt_destroy(pt_handle *h);
 PT_API const char *pt_last_error(void);
 

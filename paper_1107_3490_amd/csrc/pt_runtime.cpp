@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -984,6 +985,64 @@ PT_API int pt_selftest(const pt_model *model, int op, const double *hx, const do
     (void)hipFree(dy);
     (void)hipFree(dout);
     if (e != hipSuccess) return fail(PT_EHIP, "selftest failed: %s", hipGetErrorString(e));
+    return PT_OK;
+}
+
+// ------------------------------------------------- no-allocation variant --
+// Staging of pt_selftest_noalloc: a file-scope device array instead of
+// hipMalloc'd buffers.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is not a device
+// address: host code uses only the address hipGetSymbolAddress gives for the
+// current device (kept per device below), never the name itself.
+constexpr size_t kScratchDoubles = (size_t)1 << 21;  // 16 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array, looked up on the
+// first call on that device.
+static int scratch_base(double **out) {
+    int dev = 0;
+    PT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PT_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(PT_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PT_OK;
+}
+
+PT_API int pt_selftest_noalloc(const pt_model *model, int op, const double *hx, const double *hy, double *hout,
+                               int64_t n) {
+    size_t nin = 0, ny = 0, nout = 0;
+    int rc = selftest_args(model, op, hx, hout, n, &nin, &ny, &nout);
+    if (rc != PT_OK || n == 0) return rc;
+    // Only ops 1, 5 and 6 read the second input.
+    const size_t ny_used = (op == 1 || op == 5 || op == 6) ? ny : 0;
+    if (nin + ny_used + nout > kScratchDoubles)
+        return fail(PT_EINVAL, "op %d with n = %lld needs %zu doubles of staging; the no-allocation buffer holds %zu",
+                    op, (long long)n, nin + ny_used + nout, kScratchDoubles);
+    double *base = nullptr;
+    rc = scratch_base(&base);
+    if (rc != PT_OK) return rc;
+    double *dx = base, *dy = base + nin, *dout = base + nin + ny_used;
+    const pt::Consts k = make_consts(model, 0x1p-10);
+    PT_HIP(hipMemcpy(dx, hx, 8 * nin, hipMemcpyHostToDevice));
+    if (ny_used > 0) {
+        // The array keeps the previous call's contents: a missing second
+        // input is cleared to zeros, as pt_selftest takes it.
+        if (hy != nullptr) PT_HIP(hipMemcpy(dy, hy, 8 * ny_used, hipMemcpyHostToDevice));
+        else PT_HIP(hipMemset(dy, 0, 8 * ny_used));
+    }
+    PT_HIP(pt::launch_selftest(k, op, dx, ny_used > 0 ? dy : nullptr, dout, n, nullptr));
+    PT_HIP(hipMemcpy(hout, dout, 8 * nout, hipMemcpyDeviceToHost));
     return PT_OK;
 }
 

@@ -38,7 +38,7 @@ EXPORTS = ("pt_workspace_bytes", "pt_init", "pt_autotune", "pt_sweep", "pt_excha
            "pt_energy_method",
            "pt_observables", "pt_reset_observables", "pt_get_coords", "pt_get_running",
            "pt_get_series", "pt_get_logs", "pt_get_digests", "pt_state_bytes", "pt_get_state",
-           "pt_set_state", "pt_set_spin_limit", "pt_set_guard_scale", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_destroy",
+           "pt_set_state", "pt_set_spin_limit", "pt_set_guard_scale", "pt_time_sweeps", "pt_get_mapping", "pt_selftest", "pt_selftest_noalloc", "pt_destroy",
            "pt_last_error")
 
 
@@ -97,6 +97,8 @@ def lib():
         L.pt_set_spin_limit.argtypes = [C.c_void_p, C.c_uint32]
         L.pt_set_guard_scale.argtypes = [C.c_void_p, C.c_double]
         L.pt_selftest.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), C.c_int64]
+        L.pt_selftest_noalloc.argtypes = [P(PtModel), C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
+                                          C.c_int64]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_destroy.restype = None
         L.pt_last_error.argtypes = []
@@ -233,6 +235,19 @@ def pt_selftest(model: dict, op: int, x, y=None) -> np.ndarray:
     _check(lib().pt_selftest(C.byref(model_struct(model)), op, _ptr(x, C.c_double),
                              _ptr(yy, C.c_double) if yy is not None else None,
                              _ptr(out, C.c_double), n))
+    return out
+
+
+def pt_selftest_noalloc(model: dict, op: int, x, y=None) -> np.ndarray:
+    """pt_selftest through the entry point that allocates no device memory."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.size // 4 if op == OP_PHILOX else (x.size // MOVE_ITEM if op == OP_MOVE32 else x.size)
+    yy = np.ascontiguousarray(y, dtype=np.float64) if y is not None else None
+    nout = 2 * n if op in (OP_LJ32, OP_MOVE32) else (4 * n if op == OP_PHILOX else n)
+    out = np.zeros(nout)
+    _check(lib().pt_selftest_noalloc(C.byref(model_struct(model)), op, _ptr(x, C.c_double),
+                                     _ptr(yy, C.c_double) if yy is not None else None,
+                                     _ptr(out, C.c_double), n))
     return out
 
 
