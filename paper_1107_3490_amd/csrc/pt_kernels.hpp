@@ -474,7 +474,12 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 exact = __builtin_amdgcn_ballot_w64(!sure | (fp64_on_accept & acc)) != 0;
                 n_rescore += exact ? 1 : 0;
             }
-            if (exact) {
+            if (__builtin_expect(exact, 0)) {
+                // The FP64 re-score stays behind this (uniform, rarely taken)
+                // branch: the empty volatile asm keeps the compiler from
+                // computing it speculatively on every move, which it does
+                // otherwise at one wavefront per replica.
+                __asm__ volatile("" ::: "memory");
                 const Leaf64 s = lane_tree<0, B>(leaf64);
                 double sc = wave_tree(s.t);
                 double ab = wave_tree(s.a);
