@@ -271,6 +271,7 @@ __device__ __forceinline__ void copy_replica(double *dst, const double *src) {
 // `conflict` lists the earlier moves of the batch with |k' - k| <= 1.
 struct MoveRec {
     double dx, dy, dz, th;
+    double thb;  // th / beta: the mixed path's sure tests compare energies with it
     double xo, yo, zo;
     double dfl, dfr;
     uint64_t conflict;
@@ -290,10 +291,10 @@ __device__ __forceinline__ double tree_w(const double *v) {
 }
 
 template <int W>
-__device__ __forceinline__ float tree_wf(const double *v) {
-    if constexpr (W == 1) return (float)v[0];
-    else if constexpr (W == 2) return (float)v[0] + (float)v[1];
-    else return ((float)v[0] + (float)v[1]) + ((float)v[2] + (float)v[3]);
+__device__ __forceinline__ float tree_wf(const float *v) {
+    if constexpr (W == 1) return v[0];
+    else if constexpr (W == 2) return v[0] + v[1];
+    else return (v[0] + v[1]) + (v[2] + v[3]);
 }
 
 // ceil(log2 n), n >= 2: the depth of the pairwise tree over n leaves padded
@@ -311,6 +312,7 @@ struct SweepLds {
     double xyz[3 * Geo<B, W>::NP];
     MoveRec rec[MB];
     double part[2][2][W];
+    float partf[2][2][W];
     double partx[2][W];
     double bcast[4];
     double eblk[B * W + 1];  // energy_block
@@ -337,6 +339,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
     const double beta = T.beta[g];
     const uint32_t gid = T.slot_gid[g];
     const bool fp64_on_accept = MIXED && T.fp64_on_accept != 0;
+    const double kb_band = K.kbound * (1.0 + 0x1p-20) * T.guard_scale;
+    const double rel_band = 0x1p-50 * T.guard_scale;
     uint64_t *logrow = (T.accept_log != nullptr && t64 < T.log_cap)
                            ? T.accept_log + t64 * T.words_total + T.word_off[g]
                            : nullptr;
@@ -356,6 +360,10 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             r.dy = (unit_open(w.z) - 0.5) * K.edge;
             r.dz = (unit_open(w.w) - 0.5) * K.edge;
             r.th = -det_log(unit_open(v.x));
+            // th / beta, +inf at beta = 0; NaN where it would be so small
+            // (beta beyond 2^1000 th) that its relative rounding is not 2^-53.
+            const double thb = r.th / beta;
+            r.thb = (thb >= 0x1p-1000) ? thb : __builtin_nan("");
             const int k = r.k;
             const int ak = G::pos(k);
             r.xo = X[ak];
@@ -445,26 +453,36 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                     const bool skip = (mine && b == slot) || tid * B + b >= n;
                     return mixed_leaf(K, rx[b], ry[b], rz[b], xn, yn, zn, xo, yo, zo, skip);
                 });
-                double sm = (double)wave_tree(s.t);
-                double bsum = (double)wave_tree(s.b);
+                float smf = wave_tree(s.t);
+                float bsf = wave_tree(s.b);
                 if constexpr (W > 1) {
                     if (lane == 0) {
-                        S.part[i & 1][0][wv] = sm;
-                        S.part[i & 1][1][wv] = bsum;
+                        S.partf[i & 1][0][wv] = smf;
+                        S.partf[i & 1][1][wv] = bsf;
                     }
                     __syncthreads();
-                    sm = (double)tree_wf<W>(S.part[i & 1][0]);
-                    bsum = (double)tree_wf<W>(S.part[i & 1][1]);
+                    smf = tree_wf<W>(S.partf[i & 1][0]);
+                    bsf = tree_wf<W>(S.partf[i & 1][1]);
                 }
+                const double bsum = (double)bsf;
                 const double bs = K.kbound * bsum;
-                const double dem = K.four_eps * sm + df;  // bracket sum -> energy (Eq. 1)
-                const double bt = (bs * (1.0 + 0x1p-20) + 0x1p-50 * dabs(dem)) * T.guard_scale;
+                const double dem = K.four_eps * (double)smf + df;  // bracket sum -> energy (Eq. 1)
+                // Half-width of the band: the FP32 bound (the factor 1 + 2^-20
+                // covering the FP32 sum of its terms) and 2^-50 |dem| for the FP64
+                // roundings of dem, both widened by the guard scale.
+                const double bt = __builtin_fma(rel_band, dabs(dem), kb_band * bsum);
                 const double lo = dem - bt, hi = dem + bt;
-                // Straight-line: every outcome is computed, one is kept.
-                const bool sure_acc = (hi <= 0.0) | (beta * hi < th);
-                const bool sure_rej = (lo > 0.0) & !(beta * lo < th);
+                // Straight-line: every outcome is computed, one is kept.  With
+                // thb = th / beta > 0: hi < thb (1 - 2^-50) makes every dE <= hi
+                // accepted (dE <= 0, or beta dE < th even after rounding), and
+                // lo >= thb (1 + 2^-50) makes every dE >= lo rejected; a NaN thb
+                // (beta beyond 2^1000 th) decides nothing here.
+                const bool sure_acc = hi < r.thb * (1.0 - 0x1p-50);
+                const bool sure_rej = lo >= r.thb * (1.0 + 0x1p-50);
                 const bool broken = df == __builtin_inf();  // rejected whatever the pair sum
-                const bool sure = broken | (finite(bt) & finite(dem) & (sure_acc | sure_rej));
+                // A NaN or infinite dem (FP32 overflow) is never sure; a NaN or
+                // infinite bt fails both comparisons.
+                const bool sure = broken | (finite(dem) & (sure_acc | sure_rej));
                 acc = !broken & sure_acc;
                 de_used = dem;
                 bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
