@@ -14,8 +14,9 @@ where they do not, one task-flow launch does.
 
 Prints one JSON line.  Default workload: one chain of N = 100 monomers,
 64 temperatures geometric in [0.1, 1.5], random-walk start, seed 2; the line
-also holds sub-records of the two batched workloads (48 uneven chains; 16
-chains of N = 2000 with 256 slots each), each on its own step counts.
+also holds sub-records of the long-chain workload (N = 500, 128 slots) and of
+the two batched workloads (48 uneven chains; 16 chains of N = 2000 with 256
+slots each), each on its own step counts.
 """
 from __future__ import annotations
 
@@ -369,7 +370,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the sub-records of the batched workloads (c4, c5)")
+                    help="skip the sub-records of the other workloads (c3, c4, c5)")
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="0 auto, 1 one sweep launch per sweep, 2 persistent, 3 task flow")
     ap.add_argument("--no-tune", action="store_true", help="default mapping instead of the autotuner's")
@@ -465,8 +466,9 @@ def main():
         # The batched workloads the throughput targets are stated for, on their
         # own step counts (see sub_record).
         out["workloads"] = {
+            "c3": sub_record("c3", 200, 100, 10.0, not args.no_cpu),
             "c4": sub_record("c4", 500, 100, 10.0, not args.no_cpu),
-            "c5": sub_record("c5", 30, 30, 10.0, not args.no_cpu, cpu_chains=[0]),
+            "c5": sub_record("c5", 30, 100, 10.0, not args.no_cpu, cpu_chains=[0]),
         }
     print(json.dumps(out), flush=True)
 
