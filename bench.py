@@ -457,6 +457,16 @@ def main():
         "mixed_over_fp64": value / fp64_value,
         "roofline": roofline(w, mixed, args.steps, args.workload),
     }
+    # The mixed path with every accepted move also re-scored in the FP64 order:
+    # same decisions, running energies within 1e-9 like the FP64 path's.
+    from paper_1107_3490_amd import pt as _pt
+    acc64 = run_gpu(w, "mixed", args.steps, args.warmup, args.schedule | _pt.PT_SCHED_FP64_ON_ACCEPT,
+                    not args.no_tune)
+    acc64_value = acc64["pairs"] / (acc64["event_total_ms"] / 1e3)
+    out["mixed_fp64_on_accept"] = {"value": acc64_value, "unit": "pair interactions/s",
+                                   "ms_per_step": acc64["event_total_ms"] / args.steps,
+                                   "over_fp64": acc64_value / fp64_value,
+                                   "mapping_N_B_W": acc64["mapping"]}
     out["incl_init_and_readback"] = with_transfers(w, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
