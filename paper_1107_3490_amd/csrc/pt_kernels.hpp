@@ -185,7 +185,7 @@ __device__ __forceinline__ double bonds_wave(const double *X, const double *Y, c
 
 // The whole energy on one wavefront (lanes 0..63 of the calling block).
 template <int B, int W>
-__device__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
+__device__ __forceinline__ double energy_wave(const double *X, const double *Y, const double *Z, int n,
                               const Consts &k) {
     constexpr int BP = B * W;        // 64-row blocks
     constexpr int LC = ilog2(BP);
@@ -202,7 +202,7 @@ __device__ double energy_wave(const double *X, const double *Y, const double *Z,
 // with the same binary counter.  Called by every thread of the block; returns
 // the energy in every thread.
 template <int B, int W>
-__device__ double energy_block(const double *X, const double *Y, const double *Z, int n,
+__device__ __forceinline__ double energy_block(const double *X, const double *Y, const double *Z, int n,
                                const Consts &k, double *sh) {
     if constexpr (W == 1) {
         return energy_wave<B, W>(X, Y, Z, n, k);

@@ -257,19 +257,27 @@ def _assert_same_state(a, b):
 
 
 @pytest.mark.parametrize("schedule", [2, 3])
-@pytest.mark.parametrize("case", ["c1", "c4", "uneven_every3", "n2048", "n700_odd", "two_widths"])
+@pytest.mark.parametrize("case", ["c1", "c4", "uneven_every3", "n2048", "n700_odd", "two_widths",
+                                  "two_widths_fp64"])
 def test_persistent_schedule_equals_per_sweep(case, schedule):
     """The persistent kernel (one launch, pairwise exchange synchronisation)
     and the task flow (one launch, tasks taken in order, the later of a pair
     deciding) leave every output bit-identical to one sweep launch plus one
     exchange launch per sweep, also when the run is split over several calls.
-    two_widths: chains mapped to two and to one wavefront(s), two persistent
-    launches per call (one per wavefront count), checked against the oracle too."""
+    two_widths, two_widths_fp64: chains mapped to two and to one wavefront(s),
+    two persistent launches per call (one per wavefront count, each block taking
+    its chain's bead count per lane: 1, 2 and 4 at both widths in the FP64
+    case), checked against the oracle too."""
     mapping = None
     if case == "two_widths":
         w = I.make_workload([300, 40, 250, 61], [6, 5, 4, 3], [(0.2, 1.5), (0.3, 1.0), (0.2, 2.0), (0.5, 0.9)],
                             "walk", 94, 0, "mixed")
         sweeps, prec, chunks, mapping = 30, "mixed", [7, 23], [0x42, 0x11, 0x42, 0x11]
+    elif case == "two_widths_fp64":
+        w = I.make_workload([100, 30, 200, 90, 13, 250], [4, 3, 5, 2, 4, 3],
+                            [(0.2, 1.5), (0.3, 1.0), (0.2, 2.0), (0.5, 0.9), (0.3, 2.0), (0.25, 1.2)],
+                            "walk", 95, 0, "fp64")
+        sweeps, prec, chunks, mapping = 20, "fp64", [9, 11], [0x22, 0x12, 0x41, 0x21, 0x11, 0x42]
     elif case == "c1":
         w, sweeps, prec, chunks = I.named("c1"), 400, "mixed", [1, 150, 249]
     elif case == "c4":
@@ -289,10 +297,15 @@ def test_persistent_schedule_equals_per_sweep(case, schedule):
     b = run_gpu(w, sweeps, prec, schedule=schedule, chunks=chunks, mapping=mapping)
     assert np.all(a["persistent"] == 0) and np.all(b["persistent"] == (1 if schedule == 2 else 2))
     _assert_same_state(a, b)
-    if case == "two_widths":
+    if case in ("two_widths", "two_widths_fp64"):
         o = O.Simulation(w)
         o.run(sweeps)
         assert np.array_equal(b["coords"], o.coords) and np.array_equal(b["obs"]["perm"], o.perm)
+        if schedule == 2:
+            sim = _pt().Simulation(w, precision=prec, schedule=schedule, mapping=mapping)
+            launches = sim.time_sweeps(2)[2]
+            sim.close()
+            assert launches == 2
 
 
 def test_flow_runs_classes_that_do_not_fit():
