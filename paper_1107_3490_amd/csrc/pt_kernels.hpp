@@ -316,6 +316,7 @@ struct SweepLds {
     double partx[2][W];
     double bcast[4];
     double eblk[B * W + 1];  // energy_block
+    Consts kc;               // model constants for the rare paths of the mixed move (four wavefronts)
 };
 
 // The N moves of one sweep of the replica held by the block (Sec. 3.2), on
@@ -346,6 +347,19 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                            : nullptr;
     uint64_t logword = 0;
     uint64_t digest = (tid == 0) ? T.dig[2 * g] : 0;
+    // At four wavefronts the mixed move's rarely taken paths (the FP64
+    // re-score, about one move in 10^4, and the bond terms of a move that
+    // conflicts with an earlier accepted one) read the constants from LDS,
+    // behind a compiler barrier, so that they do not hold scalar registers
+    // across the move loop: the compiler otherwise spills scalar registers into
+    // vector lanes and restores 13 of them before every decision (N = 500 x
+    // 128: 0.457 -> 0.432 ms per sweep).
+    // At one and two wavefronts the same change made the compiler spill more
+    // (2.5% and 3.8% slower), and at 8 beads per lane (N = 2000 x 4096) it
+    // changed nothing beyond the noise, so there the constants stay where they are.
+    constexpr bool lds_consts = MIXED && W == 4 && B <= 4;
+    if constexpr (lds_consts)
+        if (tid == 0) S.kc = K;
 
     for (int m0 = 0; m0 < n; m0 += MB) {
         __syncthreads();  // commits of the previous batch visible, rec[] free
@@ -407,6 +421,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 // An accepted move of this batch touched k-1, k or k+1: redo the
                 // gather and the bond terms from the current replica (lanes 0..3
                 // of each wavefront evaluate (k-1,k) new/old, (k,k+1) new/old).
+                if constexpr (lds_consts) __asm__ volatile("" ::: "memory");
+                const Consts &KF = lds_consts ? S.kc : K;
                 auto fetch = [&](int a, double &x, double &y, double &z) {
                     const int p = G::pos(a);
                     x = X[p];
@@ -425,8 +441,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 double xa, ya, za;
                 fetch(has ? nbr : k, xa, ya, za);
                 const bool nw = (lane & 1) == 0;
-                const double fb = fene64(K, sq3(xa - (nw ? xq : xo), ya - (nw ? yq : yo),
-                                                za - (nw ? zq : zo)));
+                const double fb = fene64(KF, sq3(xa - (nw ? xq : xo), ya - (nw ? yq : yo),
+                                                 za - (nw ? zq : zo)));
                 const double fv = has ? fb : 0.0;
                 dfl = read_lane(fv, 0) - read_lane(fv, 1);
                 dfr = read_lane(fv, 2) - read_lane(fv, 3);
@@ -436,9 +452,9 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             const int owner = k >> G::LOGB, slot = k & (B - 1);
             const bool mine = (tid == owner);
 
-            auto leaf64 = [&](int b) {
-                const double en = lj64(K, sq3(rx[b] - xn, ry[b] - yn, rz[b] - zn));
-                const double eo = lj64(K, sq3(rx[b] - xo, ry[b] - yo, rz[b] - zo));
+            auto leaf64 = [&](const Consts &KL, int b) {
+                const double en = lj64(KL, sq3(rx[b] - xn, ry[b] - yn, rz[b] - zn));
+                const double eo = lj64(KL, sq3(rx[b] - xo, ry[b] - yo, rz[b] - zo));
                 const double tt = (mine && b == slot) ? 0.0 : en - eo;
                 return Leaf64{tt, dabs(tt)};
             };
@@ -498,7 +514,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 // computing it speculatively on every move, which it does
                 // otherwise at one wavefront per replica.
                 __asm__ volatile("" ::: "memory");
-                const Leaf64 s = lane_tree<0, B>(leaf64);
+                const Consts &KL = lds_consts ? S.kc : K;
+                const Leaf64 s = lane_tree<0, B>([&](int b) { return leaf64(KL, b); });
                 double sc = wave_tree(s.t);
                 double ab = wave_tree(s.a);
                 if constexpr (W > 1) {
