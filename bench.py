@@ -58,8 +58,12 @@ def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     sim = pt.Simulation(w, precision=precision, schedule=schedule, mapping=mapping)
     bpl, wpr, _ = sim.mapping()
     codes = list(mapping) if mapping is not None else [0] * len(w.n_beads)
-    tuned = sorted({(int(n), int(b), int(v)) + (("lane",) if int(c) & pt.PT_MAP_LANE else ())
-                    for n, b, v, c in zip(w.n_beads, bpl, wpr, codes)})
+    def flag(c):
+        c = int(c)
+        return (("lane",) if c & pt.PT_MAP_LANE else ("pack2",) if c & pt.PT_MAP_PACK2
+                else ("pack4",) if c & pt.PT_MAP_PACK4 else ())
+
+    tuned = sorted({(int(n), int(b), int(v)) + flag(c) for n, b, v, c in zip(w.n_beads, bpl, wpr, codes)})
     classes = sorted({(int(b), int(v)) for b, v in zip(bpl, wpr)})
     modes = sim.mapping()[2]
     persistent = bool(np.all(modes == 1))

@@ -78,8 +78,9 @@ enum pt_status {
     PT_ENOMEM = -3,        /* workspace smaller than pt_workspace_bytes()        */
     PT_EHIP = -4,          /* a HIP runtime call failed                          */
     PT_ESTATE = -5,        /* call not valid in the handle's current state       */
-    PT_EUNSUPPORTED = -6   /* chain longer than the kernels support (N > 2048), or
-                              PT_MAP_LANE with PT_MIXED                          */
+    PT_EUNSUPPORTED = -6   /* chain longer than the kernels support (N > 2048),
+                              PT_MAP_LANE with PT_MIXED, or PT_MAP_PACK2/4 with
+                              a layout other than B <= 2, W = 1                  */
 };
 
 enum pt_precision { PT_FP64 = 0, PT_MIXED = 1 };
@@ -117,7 +118,8 @@ typedef struct pt_config {
                                        and | PT_SCHED_FP64_ON_ACCEPT                 */
     const int32_t *mapping;         /* [n_chains] 16*B + W (beads per lane B in
                                        {1,2,4,8}, wavefronts per replica W in {1,2,4},
-                                       64*W*B >= N), optionally | PT_MAP_LANE, or 0
+                                       64*W*B >= N), optionally | PT_MAP_LANE,
+                                       PT_MAP_PACK2 or PT_MAP_PACK4, or 0
                                        for the default; NULL = all default.  Results
                                        do not depend on it.                            */
 } pt_config;
@@ -156,6 +158,16 @@ enum pt_schedule { PT_SCHED_AUTO = 0, PT_SCHED_PER_SWEEP = 1, PT_SCHED_PERSISTEN
  * the same either way); accepted moves then count as re-scored in
  * pt_observables. */
 enum pt_ablation { PT_SCHED_FULL_ENERGY = 16, PT_SCHED_FP64_ON_ACCEPT = 32, PT_MAP_LANE = 0x100 };
+
+/* Several replicas per wavefront for short chains (the occupancy question of
+ * Sec. 4.2: a chain of 13 beads fills 13 of a wavefront's 64 lanes).
+ * PT_MAP_PACK2 / PT_MAP_PACK4 (or-ed into a chain's mapping code, layouts
+ * 16*B + 1 with B = 1 or 2, i.e. N <= 64 B; both precisions): two or four
+ * replicas of the chain share a wavefront, 32 or 16 lanes each, every lane
+ * holding 2 B or 4 B beads; the replicas keep the layout of 16*B + 1, so all
+ * other calls treat the chain as mapped to 16*B + 1.  Sweeps run one launch per
+ * sweep (never persistent); results are those of 16*B + 1 bit for bit. */
+enum pt_map_pack { PT_MAP_PACK2 = 0x200, PT_MAP_PACK4 = 0x400 };
 
 typedef struct pt_handle pt_handle;
 
@@ -237,8 +249,10 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
                        uint8_t *h_exch_log, int64_t *exch_rows);
 
 /* Autotuner of the mapping.  For every distinct chain length of the batch it
- * times each mapping with 64 W B in [N, max(64, 4N)) -- and, for PT_FP64, one
- * lane per replica (PT_MAP_LANE) -- on the batch's chains of that length
+ * times each mapping with 64 W B in [N, max(64, 4N)) -- with W = 1 and B <= 2
+ * also packed two and four replicas per wavefront (PT_MAP_PACK2, PT_MAP_PACK4),
+ * and, for PT_FP64, one lane per replica (PT_MAP_LANE) -- on the batch's chains
+ * of that length
  * (their own slots, ladders, coordinates, precision and schedule) over
  * trial_sweeps sweeps after a warm-up, in a device workspace of its own on
  * hip_stream, and writes the fastest code to mapping_out[n_chains] (ready for

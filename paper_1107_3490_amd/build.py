@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpt.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("pt_k_run1m.hip", "pt_k_run2m.hip", "pt_k_run4m.hip", "pt_k_run1d.hip", "pt_k_run2d.hip",
-            "pt_k_run4d.hip", "pt_k_flow.hip", "pt_k_sweep.hip", "pt_k_misc.hip", "pt_k_run.hip",
+            "pt_k_run4d.hip", "pt_k_pack.hip", "pt_k_flow.hip", "pt_k_sweep.hip", "pt_k_misc.hip", "pt_k_run.hip",
             "pt_runtime.cpp")]
 ARCH = "gfx950"
 

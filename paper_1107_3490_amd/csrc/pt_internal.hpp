@@ -83,6 +83,11 @@ struct Tables {
 hipError_t launch_sweep(int bpl, int wpr, bool mixed, const Tables &T, const int32_t *slot_list,
                         int n_items, hipStream_t s);
 // One lane per replica (FP64 order): same results as launch_sweep.
+// One sweep and record of the slots in pack_list, `pack` (2 or 4) slots of one
+// chain per wavefront (entries -1: none), chains of the (bpl, 1) layout with
+// bpl = 1 or 2; n_blocks = entries / pack.
+hipError_t launch_sweep_pack(int bpl, int pack, bool mixed, const Tables &T, const int32_t *pack_list,
+                             int n_blocks, hipStream_t s);
 hipError_t launch_sweep_lane(int bpl, int wpr, const Tables &T, const int32_t *slot_list, int n_items,
                              hipStream_t s);
 hipError_t launch_energy(int bpl, int wpr, const Tables &T, const int32_t *conf_list, int n_items,

@@ -67,6 +67,7 @@ struct Layout {
     int n_chains = 0, total = 0;
     std::vector<int> bpl, wpr;        // per chain
     std::vector<char> lane;           // per chain: one lane per replica
+    std::vector<char> pack;           // per chain: replicas per wavefront (1, 2 or 4)
     std::vector<int64_t> coord_off;   // per conformation (doubles)
     std::vector<int64_t> word_off;    // per slot
     int64_t coord_total = 0, words_total = 0;
@@ -103,11 +104,15 @@ int validate(const pt_model *m, const pt_config *c) {
         if (c->mapping != nullptr && c->mapping[ch] != 0) {
             const int code = c->mapping[ch], B = (code >> 4) & 15, W = code & 15;
             const bool okb = B == 1 || B == 2 || B == 4 || B == 8, okw = W == 1 || W == 2 || W == 4;
-            if (!okb || !okw || (code & ~(0xFF | PT_MAP_LANE)) != 0)
+            const int flags = code & ~0xFF;
+            if (!okb || !okw || (flags != 0 && flags != PT_MAP_LANE && flags != PT_MAP_PACK2 && flags != PT_MAP_PACK4))
                 return fail(PT_EINVAL, "chain %d: mapping %d is not 16*B + W with B in {1,2,4,8}, W in {1,2,4} "
-                                       "(optionally + PT_MAP_LANE)", ch, code);
+                                       "(optionally + one of PT_MAP_LANE, PT_MAP_PACK2, PT_MAP_PACK4)", ch, code);
             if ((code & PT_MAP_LANE) != 0 && c->precision != PT_FP64)
                 return fail(PT_EUNSUPPORTED, "chain %d: mapping PT_MAP_LANE runs the FP64 order only", ch);
+            if ((flags == PT_MAP_PACK2 || flags == PT_MAP_PACK4) && !(W == 1 && (B == 1 || B == 2)))
+                return fail(PT_EUNSUPPORTED, "chain %d: PT_MAP_PACK2 / PT_MAP_PACK4 take the layouts B = 1 or 2, "
+                                             "W = 1 (N <= 128)", ch);
             if (64 * W * B < c->n_beads[ch])
                 return fail(PT_EINVAL, "chain %d: mapping B=%d W=%d holds %d < %d beads", ch, B, W, 64 * W * B, c->n_beads[ch]);
         }
@@ -173,6 +178,7 @@ Layout plan(const pt_config *c) {
     L.bpl.resize(c->n_chains);
     L.wpr.resize(c->n_chains);
     L.lane.assign(c->n_chains, 0);
+    L.pack.assign(c->n_chains, 1);
     L.coord_off.resize(total);
     L.word_off.resize(total);
     int g = 0;
@@ -181,6 +187,7 @@ Layout plan(const pt_config *c) {
             L.bpl[ch] = (c->mapping[ch] >> 4) & 15;
             L.wpr[ch] = c->mapping[ch] & 15;
             L.lane[ch] = (c->mapping[ch] & PT_MAP_LANE) != 0;
+            L.pack[ch] = (c->mapping[ch] & PT_MAP_PACK4) ? 4 : (c->mapping[ch] & PT_MAP_PACK2) ? 2 : 1;
         } else {
             mapping(c->n_beads[ch], &L.bpl[ch], &L.wpr[ch]);
         }
@@ -194,8 +201,9 @@ Layout plan(const pt_config *c) {
     L.log_cap = c->log_capacity;
     L.series_cap = c->series_capacity;
     // lists: per class slot lists (total) + chain lists (n_chains) + the
-    // conformation lists of the persistent launches (total)
-    L.lists_len = 2 * L.total + L.n_chains;
+    // conformation lists of the persistent launches (total) + the slot lists
+    // of the packed classes (total, each chain padded by at most 3)
+    L.lists_len = 3 * L.total + 4 * L.n_chains;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     const size_t S = (size_t)L.total, C = (size_t)L.n_chains;
@@ -248,12 +256,15 @@ double fene_y(const pt::Consts &k, const double *a, const double *b) {
 struct Class {
     int bpl = 0, wpr = 0;
     bool lane = false;        // one lane per replica (FP64 order, per-sweep launches)
+    int pack = 1;             // replicas per wavefront (2, 4: per-sweep launches of k_sweep_pack)
     bool persistent = false;  // whole sweeps run by a persistent launch (of its run group)
     bool flow = false;        // whole sweeps run by one task-flow launch (slots do not all fit)
     bool whole() const { return persistent || flow; }
     int n_slots = 0, n_chains = 0, max_pairs = 0;
     int32_t *d_slots = nullptr;   // slot (= starting conformation) list
     int32_t *d_chains = nullptr;  // chain list
+    int32_t *d_pack = nullptr;    // packed classes: slot list, each chain padded to a multiple of pack with -1
+    int n_pack_blocks = 0;
     int64_t resident = 0;         // task flow: blocks the device holds at once
 };
 
@@ -291,6 +302,7 @@ namespace {
 
 hipError_t launch_class_sweep(const pt_handle *h, const Class &c, hipStream_t s) {
     if (c.lane) return pt::launch_sweep_lane(c.bpl, c.wpr, h->T, c.d_slots, c.n_slots, s);
+    if (c.pack > 1) return pt::launch_sweep_pack(c.bpl, c.pack, h->mixed, h->T, c.d_pack, c.n_pack_blocks, s);
     return pt::launch_sweep(c.bpl, c.wpr, h->mixed, h->T, c.d_slots, c.n_slots, s);
 }
 
@@ -449,8 +461,8 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     h->d_tmp = (double *)(w + L.o_tmp);
 
     // Classes by (beads per lane, wavefronts per replica, one lane per replica).
-    std::map<std::tuple<int, int, int>, std::vector<int>> cls_chains;
-    for (int ch = 0; ch < C; ++ch) cls_chains[{L.bpl[ch], L.wpr[ch], (int)L.lane[ch]}].push_back(ch);
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> cls_chains;
+    for (int ch = 0; ch < C; ++ch) cls_chains[{L.bpl[ch], L.wpr[ch], (int)L.lane[ch], (int)L.pack[ch]}].push_back(ch);
     std::vector<int32_t> lists;
     lists.reserve(L.lists_len);
     std::vector<std::vector<int>> class_chains;
@@ -459,6 +471,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
         cl.bpl = std::get<0>(kv.first);
         cl.wpr = std::get<1>(kv.first);
         cl.lane = std::get<2>(kv.first) != 0;
+        cl.pack = std::get<3>(kv.first);
         const size_t slot_at = lists.size();
         for (int ch : kv.second)
             for (int s = 0; s < cfg->n_slots[ch]; ++s) lists.push_back(chain_slot0[ch] + s);
@@ -471,6 +484,15 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
         cl.n_chains = (int)kv.second.size();
         cl.d_slots = (int32_t *)(w + L.o_lists) + slot_at;
         cl.d_chains = (int32_t *)(w + L.o_lists) + chain_at;
+        if (cl.pack > 1) {
+            const size_t pack_at = lists.size();
+            for (int ch : kv.second) {
+                const int ns = cfg->n_slots[ch], padded = (ns + cl.pack - 1) / cl.pack * cl.pack;
+                for (int s = 0; s < padded; ++s) lists.push_back(s < ns ? chain_slot0[ch] + s : -1);
+            }
+            cl.d_pack = (int32_t *)(w + L.o_lists) + pack_at;
+            cl.n_pack_blocks = (int)((lists.size() - pack_at) / cl.pack);
+        }
         h->classes.push_back(cl);
         class_chains.push_back(kv.second);
     }
@@ -490,7 +512,7 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
     if (sched != PT_SCHED_PER_SWEEP) {
         std::vector<int> order;
         for (int i = 0; i < (int)h->classes.size(); ++i)
-            if (!h->classes[i].lane) order.push_back(i);
+            if (!h->classes[i].lane && h->classes[i].pack == 1) order.push_back(i);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             const Class &x = h->classes[a], &y = h->classes[b];
             return x.wpr != y.wpr ? x.wpr < y.wpr : x.bpl > y.bpl;
@@ -539,7 +561,8 @@ PT_API int pt_init(const pt_model *model, const pt_config *cfg, void *d_workspac
             }
         }
         for (Class &cl : h->classes) {
-            cl.flow = !cl.lane && !cl.persistent && (sched == PT_SCHED_FLOW || 64 * cl.wpr * cl.bpl >= kFlowMinSlots);
+            cl.flow = !cl.lane && cl.pack == 1 && !cl.persistent &&
+                      (sched == PT_SCHED_FLOW || 64 * cl.wpr * cl.bpl >= kFlowMinSlots);
             if (cl.flow) {
                 hipError_t e0 = pt::flow_capacity(cl.bpl, cl.wpr, h->mixed, &cl.resident);
                 if (e0 != hipSuccess) return fin(fail(PT_EHIP, "occupancy query failed: %s", hipGetErrorString(e0)));
@@ -936,7 +959,8 @@ PT_API int pt_get_mapping(pt_handle *h, int32_t *bpl, int32_t *wpr, int32_t *per
         if (persistent) {
             persistent[c] = 0;
             for (const Class &cl : h->classes)
-                if (cl.bpl == h->L.bpl[c] && cl.wpr == h->L.wpr[c] && cl.lane == (h->L.lane[c] != 0))
+                if (cl.bpl == h->L.bpl[c] && cl.wpr == h->L.wpr[c] && cl.lane == (h->L.lane[c] != 0) &&
+                    cl.pack == h->L.pack[c])
                     persistent[c] = cl.persistent ? 1 : cl.flow ? 2 : 0;
         }
     }
@@ -1241,6 +1265,10 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
                 const int np = 64 * W * B;
                 if (np >= n && np < std::max(65, 4 * n)) cand.push_back(16 * B + W);
             }
+        // Short chains can share a wavefront, two or four replicas of 32 or 16 lanes.
+        for (int B : {1, 2})
+            if (64 * B >= n && 64 * B < std::max(65, 4 * n))
+                for (int f : {PT_MAP_PACK2, PT_MAP_PACK4}) cand.push_back(f | (16 * B + 1));
         // The FP64 order can also run one lane per replica (in the default layout).
         if (cfg->precision == PT_FP64) {
             int b = 0, w = 0;
@@ -1329,7 +1357,7 @@ PT_API int pt_autotune(const pt_model *model, const pt_config *cfg, int32_t tria
                 int code = 0;
                 double best_ms = 0.0;
                 for (const auto &x : timed[n])
-                    if ((x.first & PT_MAP_LANE) == 0 && (x.first & 15) == W && (code == 0 || x.second < best_ms)) {
+                    if ((x.first & ~0xFF) == 0 && (x.first & 15) == W && (code == 0 || x.second < best_ms)) {
                         code = x.first;
                         best_ms = x.second;
                     }

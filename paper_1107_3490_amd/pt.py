@@ -28,6 +28,7 @@ PT_SCHED_AUTO, PT_SCHED_PER_SWEEP, PT_SCHED_PERSISTENT, PT_SCHED_FLOW = 0, 1, 2,
 # (full energy after every sweep) or into a chain's mapping code (one lane per
 # replica, FP64 only).
 PT_SCHED_FULL_ENERGY, PT_SCHED_FP64_ON_ACCEPT, PT_MAP_LANE = 16, 32, 0x100
+PT_MAP_PACK2, PT_MAP_PACK4 = 0x200, 0x400
 PT_ENERGY_FP64_ORDER, PT_ENERGY_PAIR_PER_THREAD = 0, 1
 
 # Diagnostic ops of pt_selftest.
@@ -258,7 +259,7 @@ def pt_destroy(h: int) -> None:
 def autotune(w, precision: Optional[str] = None, schedule: int = PT_SCHED_AUTO,
              trial_sweeps: int = 20) -> np.ndarray:
     """pt_autotune on workload w: one mapping code (16 B + W, possibly
-    | PT_MAP_LANE for FP64) per chain."""
+    | PT_MAP_PACK2 or PT_MAP_PACK4, or | PT_MAP_LANE for FP64) per chain."""
     import torch
 
     prec = precision or w.precision

@@ -136,7 +136,7 @@ def test_autotune_considers_one_lane_per_replica_for_fp64():
     print(f"\n[case] autotune fp64: {[hex(int(c)) for c in codes]}", flush=True)
     for n, c in zip(w.n_beads, codes):
         c = int(c)
-        assert c & ~(0xFF | pt.PT_MAP_LANE) == 0
+        assert c & ~(0xFF | pt.PT_MAP_LANE | pt.PT_MAP_PACK2 | pt.PT_MAP_PACK4) == 0
         b, wv = (c >> 4) & 15, c & 15
         assert b in (1, 2, 4, 8) and wv in (1, 2, 4) and n <= 64 * b * wv
     _assert_same_state(run_gpu(w, 5, "fp64", mapping=codes), run_gpu(w, 5, "fp64"))

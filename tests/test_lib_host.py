@@ -114,7 +114,7 @@ def test_mapping_override_is_validated(L):
     base = pt.pt_workspace_bytes(m, cfg)
     assert base > 0
     for code, ok in ((0x21, True), (0x12, True), (0x14, True), (0x84, True), (0x11, False),
-                     (0x31, False), (0x23, False), (0x121, True), (0x111, False), (0x221, False),
+                     (0x31, False), (0x23, False), (0x121, True), (0x111, False), (0x221, True), (0x821, False),
                      (-1, False)):
         mp = np.array([code], dtype=np.int32)
         cfg.mapping = pt._ptr(mp, C.c_int32)
@@ -126,6 +126,24 @@ def test_mapping_override_is_validated(L):
     mp = np.array([0x84], dtype=np.int32)
     cfg.mapping = pt._ptr(mp, C.c_int32)
     assert L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) > base
+
+
+def test_packing_flags_are_validated(L):
+    """Two or four replicas per wavefront take the layouts 16 B + 1 with B = 1
+    or 2 (both precisions), one packing flag at a time, not with one lane per
+    replica."""
+    m = pt.model_struct(I.model_params())
+    w = I.make_workload([60], [3], [(0.1, 1.5)], "straight", 1, 0, "mixed")
+    cfg, keep = _cfg(w, precision=pt.PT_MIXED)
+    for code, ok in ((pt.PT_MAP_PACK2 | 0x11, True), (pt.PT_MAP_PACK4 | 0x11, True), (pt.PT_MAP_PACK2 | 0x21, True),
+                     (pt.PT_MAP_PACK4 | 0x21, True), (pt.PT_MAP_PACK2 | 0x12, False), (pt.PT_MAP_PACK4 | 0x41, False),
+                     (pt.PT_MAP_PACK2 | pt.PT_MAP_PACK4 | 0x11, False), (pt.PT_MAP_LANE | pt.PT_MAP_PACK2 | 0x11, False),
+                     (0x800 | 0x11, False)):
+        mp = np.array([code], dtype=np.int32)
+        cfg.mapping = pt._ptr(mp, C.c_int32)
+        assert (L.pt_workspace_bytes(C.byref(m), C.byref(cfg)) > 0) == ok, hex(code)
+        if not ok:
+            assert "PT_MAP_PACK" in L.pt_last_error().decode()
 
 
 def test_ablation_flags_are_validated(L):
