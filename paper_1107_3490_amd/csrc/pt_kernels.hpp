@@ -1068,10 +1068,15 @@ __global__ __launch_bounds__(64 * W) void k_exchange(const Tables T, const int32
 
 // ---------------------------------------------------------- persistent run --
 // Spin (one thread) until *p >= v; false after a timeout or when another block
-// reported one, which also ends the waiting of every other block.
+// reported one, which also ends the waiting of every other block.  The polls
+// are relaxed (an acquiring load would invalidate the caches on every poll);
+// the acquire fence after the successful one pairs with the writer's release.
 __device__ __forceinline__ bool wait_ge(const int64_t *p, int64_t v, int32_t *err, uint32_t limit) {
     for (uint32_t it = 0; it < limit; ++it) {
-        if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         __builtin_amdgcn_s_sleep(2);
     }
@@ -1114,10 +1119,10 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
         sweep_moves<B, W, MIXED>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
         sweep_record<B, W>(T, S, g, q, n, t64, E, Bd, n_acc, n_rescore);
         if (!(T.exchange_every > 0 && (t64 + 1) % T.exchange_every == 0)) continue;
-        // Publish this conformation at slot g.
+        // Publish this conformation at slot g: the block's writes, then (after
+        // the barrier, which completes them) thread 0's releasing flag store.
         copy_replica<B, W, G::NT>(cq, S.xyz);
         if (tid == 0) T.perm[g] = q;
-        __threadfence();
         __syncthreads();
         if (tid == 0) __hip_atomic_store(&T.done[g], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const int i = g - s0;
@@ -1127,10 +1132,11 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
         if (lower) {
             // Every wavefront takes part: the FP64-order energies of a decision
             // inside the band use the whole block.
+            // wait_ge's acquire (thread 0), then the barrier, orders the
+            // block's reads of the partner's data after the partner's flag.
             if (tid == 0) s_ok = wait_ge(&T.done[g + 1], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
             __syncthreads();
             if (s_ok) {
-                __threadfence();
                 const int q2 = T.perm[g + 1];
                 double e1 = E, bb1 = Bd;
                 double e2 = T.e_run[q2], bb2 = T.b_run[q2];
@@ -1166,7 +1172,6 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
                         S.bcast[1] = Bd;
                     }
                     exch_commit(T, g, e, q, q2, acc, band);
-                    __threadfence();
                     __hip_atomic_store(&T.dec[g + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     s_slot = acc ? g + 1 : g;
                 }
@@ -1178,12 +1183,9 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
             if (upper) {
                 if (tid == 0) ok = wait_ge(&T.dec[g], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
                 ok = __builtin_amdgcn_readfirstlane(ok);
-                if (ok) {
-                    __threadfence();
-                    if (tid == 0) {
-                        S.bcast[0] = T.e_run[q];
-                        S.bcast[1] = T.b_run[q];
-                    }
+                if (ok && tid == 0) {  // after wait_ge's acquire
+                    S.bcast[0] = T.e_run[q];
+                    S.bcast[1] = T.b_run[q];
                     slot = T.slot_of[q];
                 }
             } else if (tid == 0) {
