@@ -1280,10 +1280,11 @@ __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Ta
         const int n = T.chain_n[c];
         // The slot's conformation for sweep t64.
         if (s > 0) {
+            // wait_ge's acquire (thread 0), then the barrier, orders the
+            // block's reads of the conformation after the flag.
             if (tid == 0) s_flag = wait_ge(&T.flow_ready[g], t64, T.err, T.spin_limit) ? 1 : 0;
             __syncthreads();
             if (!s_flag) return;  // a timeout: the error flag is set
-            __threadfence();
         }
         const int q = T.perm[g];
         double *cq = T.coords + T.coord_off[q];
@@ -1305,7 +1306,9 @@ __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Ta
         const int par = (int)(e & 1);
         const bool lower = due && i >= par && ((i - par) & 1) == 0 && i + 1 < R;
         const bool upper = due && i >= 1 + par && ((i - 1 - par) & 1) == 0;
-        __threadfence();  // coordinates, running energy and record published
+        // Coordinates, running energy and record are published by the barrier
+        // (which completes the block's writes) and thread 0's releasing store
+        // or arrival.
         __syncthreads();
         if (!lower && !upper) {
             if (tid == 0) __hip_atomic_store(&T.flow_ready[g], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1318,8 +1321,7 @@ __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Ta
             s_flag = (int32_t)(old & 1);  // 1: the partner has arrived, this task decides
         }
         __syncthreads();
-        if (!s_flag) continue;
-        __threadfence();
+        if (!s_flag) continue;  // else thread 0's arrival acquired the partner's publication
         const int q1 = T.perm[glow], q2 = T.perm[glow + 1];
         double e1 = T.e_run[q1], bb1 = T.b_run[q1];
         double e2 = T.e_run[q2], bb2 = T.b_run[q2];
@@ -1343,7 +1345,6 @@ __global__ __launch_bounds__(64 * W, (B * W >= 16) ? 3 : 1) void k_flow(const Ta
                 T.b_run[q2] = bb2;
             }
             exch_commit(T, glow, e, q1, q2, acc, band);
-            __threadfence();
             __hip_atomic_store(&T.flow_ready[glow], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&T.flow_ready[glow + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
