@@ -1222,8 +1222,11 @@ extern __shared__ double pt_dyn_lds[];
 // share the launch: each block takes its chain's B from chain_bpl.  The run
 // starts at the device's run counters, which only a later kernel advances.
 // MINW is the minimum number of wavefronts per SIMD the registers must allow:
-// 1 for batches that fit anyway (no spills), more for dense batches.
-template <int W, bool MIXED, int MINW>
+// 1 for batches that fit anyway (no spills), more for dense batches.  MAXB is
+// the largest bead count per lane built in: 4 leaves out the 8-bead body,
+// whose registers make the dense build spill in every body (the 48 uneven
+// chains at two wavefronts: 0.609 -> 0.606 ms per sweep).
+template <int W, bool MIXED, int MINW, int MAXB = 8>
 __global__ __launch_bounds__(64 * W, MINW) void k_run(const Tables T, const int32_t *__restrict__ list,
                                                       int64_t n_sweeps) {
     __shared__ int32_t s_slot, s_ok;
@@ -1234,7 +1237,10 @@ __global__ __launch_bounds__(64 * W, MINW) void k_run(const Tables T, const int3
         case 1: run_body<1, W, MIXED>(T, *reinterpret_cast<SweepLds<1, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
         case 2: run_body<2, W, MIXED>(T, *reinterpret_cast<SweepLds<2, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
         case 4: run_body<4, W, MIXED>(T, *reinterpret_cast<SweepLds<4, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
-        case 8: run_body<8, W, MIXED>(T, *reinterpret_cast<SweepLds<8, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0); break;
+        case 8:
+            if constexpr (MAXB >= 8)
+                run_body<8, W, MIXED>(T, *reinterpret_cast<SweepLds<8, W> *>(pt_dyn_lds), s_slot, s_ok, q, n_sweeps, t0, e0);
+            break;
         default: break;  // not a built class (the host never lists one)
     }
 }
