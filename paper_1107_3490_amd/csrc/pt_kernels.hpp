@@ -416,6 +416,11 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r.conflict)) |
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(r.conflict >> 32)) << 32);
             const double th = r.th;
+            // The mixed decision's thresholds, formed before the pair sum: read
+            // after the W-wavefront barrier, th/beta would put an LDS load on
+            // the chain of dependent moves.
+            const double thb = MIXED ? r.thb : 0.0;
+            const double thb_lo = thb * (1.0 - 0x1p-50), thb_hi = thb * (1.0 + 0x1p-50);
             double xo = r.xo, yo = r.yo, zo = r.zo, dfl = r.dfl, dfr = r.dfr;
             if ((cf & bits) != 0) {
                 // An accepted move of this batch touched k-1, k or k+1: redo the
@@ -493,8 +498,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 // accepted (dE <= 0, or beta dE < th even after rounding), and
                 // lo >= thb (1 + 2^-50) makes every dE >= lo rejected; a NaN thb
                 // (beta beyond 2^1000 th) decides nothing here.
-                const bool sure_acc = hi < r.thb * (1.0 - 0x1p-50);
-                const bool sure_rej = lo >= r.thb * (1.0 + 0x1p-50);
+                const bool sure_acc = hi < thb_lo;
+                const bool sure_rej = lo >= thb_hi;
                 const bool broken = df == __builtin_inf();  // rejected whatever the pair sum
                 // A NaN or infinite dem (FP32 overflow) is never sure; a NaN or
                 // infinite bt fails both comparisons.
