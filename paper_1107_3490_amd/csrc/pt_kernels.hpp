@@ -465,6 +465,10 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             };
             bool acc = false;
             double de_used = 0.0, bm = 0.0;
+            // The FP32 score's bound term is formed only for an accepted move
+            // (in the commit), off the path of a rejected one.
+            double bsum_acc = 0.0;
+            bool bm_fp32 = false;
             bool exact = !MIXED;
             if constexpr (MIXED) {
                 const LeafMx s = lane_tree<0, B>([&](int b) {
@@ -486,7 +490,6 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                     bsf = tree_wf<W>(S.partf[i & 1][1]);
                 }
                 const double bsum = (double)bsf;
-                const double bs = K.kbound * bsum;
                 const double dem = K.four_eps * (double)smf + df;  // bracket sum -> energy (Eq. 1)
                 // Half-width of the band: the FP32 bound (the factor 1 + 2^-20
                 // covering the FP32 sum of its terms) and 2^-50 |dem| for the FP64
@@ -506,7 +509,8 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 const bool sure = broken | (finite(dem) & (sure_acc | sure_rej));
                 acc = !broken & sure_acc;
                 de_used = dem;
-                bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
+                bsum_acc = bsum;
+                bm_fp32 = true;
                 // uniform: a scalar branch; with fp64_on_accept every accepted
                 // move is re-scored as well, so that the running energy adds
                 // FP64-order differences only
@@ -538,8 +542,14 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
                 acc = (de <= 0.0) || (beta * de < th);
                 de_used = de;
                 bm = bound64(log2c(n), ab, dfl, dfr, de);
+                bm_fp32 = false;
             }
             if (__builtin_amdgcn_ballot_w64(acc) != 0) {
+                // FP32 score: K.kbound sum (S^2 + S), the factor 1 + 2^-20 for
+                // the FP32 sum of its terms, and the FP64 roundings of dE.
+                if (bm_fp32)
+                    bm = (K.kbound * bsum_acc) * (1.0 + 0x1p-20) +
+                         0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(de_used));
                 if (mine) {
                     const int ak = G::pos(k);
                     X[ak] = xn;
