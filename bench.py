@@ -165,7 +165,9 @@ def paper_protocol(n_beads=55, sweeps=4000, every=1000, edge=0.02,
     host-to-device copies, the sweeps and the read-back of every conformation
     (the paper's timing includes its copies); S_p = t_CPU / t_GPU with t_CPU the
     oracle on one core, timed on a few replicas and scaled by n_r (its cost is
-    linear in n_r).  Context only: the paper's hardware and numbers differ."""
+    linear in n_r).  The mapping is the autotuner's (chosen before the timed run:
+    one or several replicas per wavefront), and the default one is timed beside
+    it.  Context only: the paper's hardware and numbers differ."""
     import torch
     from oracle import oracle as O
     from paper_1107_3490_amd import inputs as I
@@ -182,20 +184,27 @@ def paper_protocol(n_beads=55, sweeps=4000, every=1000, edge=0.02,
     sim.run(1000)
     cpu_per_replica_sweep = (time.perf_counter() - t0) / (4 * 1000)
     rows = []
+    def t_run(w, prec, mapping):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = pt.Simulation(w, precision=prec, mapping=mapping)
+        s.sweep(sweeps)
+        s.coords()
+        s.observables()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        s.close()
+        return t
+
     for nr in replicas:
         w = workload(nr)
         for prec in ("mixed", "fp64"):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s = pt.Simulation(w, precision=prec)
-            s.sweep(sweeps)
-            s.coords()
-            s.observables()
-            torch.cuda.synchronize()
-            t_gpu = time.perf_counter() - t0
-            s.close()
+            code = int(pt.autotune(w, prec, trial_sweeps=20)[0])
+            t_gpu = t_run(w, prec, [code])
+            t_default = t_run(w, prec, None)
             t_cpu = cpu_per_replica_sweep * nr * sweeps
-            rows.append({"n_r": nr, "precision": prec, "t_gpu_s": t_gpu, "t_cpu_1core_s": t_cpu,
+            rows.append({"n_r": nr, "precision": prec, "mapping": hex(code), "t_gpu_s": t_gpu,
+                         "t_gpu_default_mapping_s": t_default, "t_cpu_1core_s": t_cpu,
                          "S_p": t_cpu / t_gpu,
                          "pair_per_s": w.pair_interactions_per_sweep() * sweeps / t_gpu})
     return {"protocol": f"N={n_beads}, edge {edge}, {sweeps} sweeps, exchange every {every}, "
