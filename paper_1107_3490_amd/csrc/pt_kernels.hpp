@@ -1035,6 +1035,36 @@ __device__ __forceinline__ void exch_commit(const Tables &T, int g, int64_t e, i
     T.dig[2 * g + 1] = mix64(T.dig[2 * g + 1] ^ (((uint64_t)e << 1) | (acc ? 1u : 0u)));
 }
 
+// The words exch_commit updates, read ahead of the decision by the persistent
+// kernel's deciding block (their last writer handed the slot on through the
+// handshakes this block has already acquired), so that the commit stores
+// without waiting for loads.
+struct ExchBook {
+    int64_t c1, c2, c4;
+    uint64_t dig;
+};
+
+__device__ __forceinline__ ExchBook exch_book(const Tables &T, int g) {
+    const int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
+    return ExchBook{cnt[1], cnt[2], cnt[4], T.dig[2 * g + 1]};
+}
+
+__device__ __forceinline__ void exch_commit_from(const Tables &T, const ExchBook &bk, int g, int64_t e, int q1,
+                                                 int q2, bool acc, bool band) {
+    int64_t *cnt = T.counts + (int64_t)g * PT_NCOUNTS;
+    cnt[1] = bk.c1 + 1;
+    if (band) cnt[4] = bk.c4 + 1;
+    if (acc) {
+        cnt[2] = bk.c2 + 1;
+        T.perm[g] = q2;
+        T.perm[g + 1] = q1;
+        T.slot_of[q1] = g + 1;
+        T.slot_of[q2] = g;
+    }
+    if (T.exch_log != nullptr && e < T.log_cap) T.exch_log[e * T.total_slots + g] = acc ? 1 : 0;
+    T.dig[2 * g + 1] = mix64(bk.dig ^ (((uint64_t)e << 1) | (acc ? 1u : 0u)));
+}
+
 // One exchange step for the chains in `list`: block p of a chain (W
 // wavefronts) handles the pair (i, i+1), i = (e mod 2) + 2p.
 template <int B, int W>
@@ -1149,7 +1179,11 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
             // inside the band use the whole block.
             // wait_ge's acquire (thread 0), then the barrier, orders the
             // block's reads of the partner's data after the partner's flag.
-            if (tid == 0) s_ok = wait_ge(&T.done[g + 1], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
+            ExchBook bk{};
+            if (tid == 0) {
+                bk = exch_book(T, g);
+                s_ok = wait_ge(&T.done[g + 1], t64 + 1, T.err, T.spin_limit) ? 1 : 0;
+            }
             __syncthreads();
             if (s_ok) {
                 const int q2 = T.perm[g + 1];
@@ -1186,7 +1220,7 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
                         S.bcast[0] = E;
                         S.bcast[1] = Bd;
                     }
-                    exch_commit(T, g, e, q, q2, acc, band);
+                    exch_commit_from(T, bk, g, e, q, q2, acc, band);
                     __hip_atomic_store(&T.dec[g + 1], t64 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     s_slot = acc ? g + 1 : g;
                 }
