@@ -227,10 +227,10 @@ __global__ __launch_bounds__(64) void k_sweep_pack(const Tables T, const int32_t
         wave_sync();
         const int nb = (n - m0 < L) ? (n - m0) : L;
         uint64_t bits = 0;
-        for (int i = 0; i < nb; ++i) {
-            const MoveRec r = S.rec[grp][i];
+        auto one_move = [&](const int i, const MoveRec &r) {
             const int k = r.k;
             const double th = r.th;
+            const double thb_lo = r.thb * (1.0 - 0x1p-50), thb_hi = r.thb * (1.0 + 0x1p-50);
             double xo = r.xo, yo = r.yo, zo = r.zo, dfl = r.dfl, dfr = r.dfr;
             if ((r.conflict & bits) != 0) {
                 // An accepted move of this batch touched k-1, k or k+1: lanes
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(64) void k_sweep_pack(const Tables T, const int32_t
             const int owner = k / B, slot = k % B;
             const bool mine = (ll == owner);
             bool acc = false, need = !MIXED;
-            double de_used = 0.0, bm = 0.0;
+            double de_used = 0.0, bm = 0.0, bsum_acc = 0.0;
             if constexpr (MIXED) {
                 const LeafMx s = lane_tree<0, B>([&](int b) {
                     const bool skip = (mine && b == slot) || ll * B + b >= n;
@@ -267,17 +267,16 @@ __global__ __launch_bounds__(64) void k_sweep_pack(const Tables T, const int32_t
                 const float smf = group_tree<L>(s.t);
                 const float bsf = group_tree<L>(s.b);
                 const double bsum = (double)bsf;
-                const double bs = K.kbound * bsum;
                 const double dem = K.four_eps * (double)smf + df;
                 const double bt = __builtin_fma(rel_band, dabs(dem), kb_band * bsum);
                 const double lo = dem - bt, hi = dem + bt;
-                const bool sure_acc = hi < r.thb * (1.0 - 0x1p-50);
-                const bool sure_rej = lo >= r.thb * (1.0 + 0x1p-50);
+                const bool sure_acc = hi < thb_lo;
+                const bool sure_rej = lo >= thb_hi;
                 const bool broken = df == __builtin_inf();
                 const bool sure = broken | (finite(dem) & (sure_acc | sure_rej));
                 acc = !broken & sure_acc;
                 de_used = dem;
-                bm = bs * (1.0 + 0x1p-20) + 0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(dem));
+                bsum_acc = bsum;
                 need = !sure | (fp64_on_accept & acc);
                 n_rescore += need ? 1 : 0;
             }
@@ -301,6 +300,11 @@ __global__ __launch_bounds__(64) void k_sweep_pack(const Tables T, const int32_t
                 }
             }
             if (acc) {
+                // The FP32 score's bound term, formed for accepted moves only
+                // (the arithmetic of sweep_moves).
+                if (MIXED && !need)
+                    bm = (K.kbound * bsum_acc) * (1.0 + 0x1p-20) +
+                         0x1p-52 * (2.0 * (dabs(dfl) + dabs(dfr)) + dabs(de_used));
                 if (mine) {
                     const int ak = GE::pos(k);
                     X[ak] = xn;
@@ -320,6 +324,16 @@ __global__ __launch_bounds__(64) void k_sweep_pack(const Tables T, const int32_t
                 bits |= 1ull << i;
             }
             wave_sync();
+        };
+        // The next move's record is read while the current move runs, in two
+        // alternating register sets (as in sweep_moves at one wavefront).
+        MoveRec ra = S.rec[grp][0];
+        for (int i = 0; i < nb; i += 2) {
+            const MoveRec rb = S.rec[grp][(i + 1 < L) ? i + 1 : L - 1];
+            one_move(i, ra);
+            if (i + 1 >= nb) break;
+            ra = S.rec[grp][(i + 2 < L) ? i + 2 : L - 1];
+            one_move(i + 1, rb);
         }
         logword |= bits << (m0 & 63);
         if (ll == 0 && (((m0 + L) & 63) == 0 || m0 + L >= n)) {
