@@ -71,6 +71,19 @@ __device__ __forceinline__ LeafMx mixed_leaf(const Consts &K, double x, double y
 
 __device__ __forceinline__ double dabs(double v) { return __builtin_fabs(v); }
 
+// The value of lane l ^ 32 (v_permlane32_swap of two copies leaves the lower
+// half's value in the first output and the upper half's in the second, in
+// every lane).
+__device__ __forceinline__ uint32_t other_half(uint32_t v) {
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? p[0] : p[1];
+}
+__device__ __forceinline__ double other_half(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = other_half((uint32_t)b), hi = other_half((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // Bound on |E_run - exact sum of the FP64-order terms| added by one accepted
@@ -326,7 +339,7 @@ struct SweepLds {
 // conflict mask.  The serial part of a move is the pair loop over the lane's
 // beads in registers, the butterflies, one barrier to combine the W wavefront
 // sums (W > 1), and the decision, taken identically by every wavefront.
-template <int B, int W, bool MIXED>
+template <int B, int W, bool MIXED, bool SPLIT_OK = true>
 __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, double (&rx)[B],
                                             double (&ry)[B], double (&rz)[B], int g, int n,
                                             uint32_t t, int64_t t64, double &E, double &Bd,
@@ -365,9 +378,24 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
         __syncthreads();  // commits of the previous batch visible, rec[] free
         if (wv == 0) {
             // ---- prologue: move m0 + lane (Philox counters (m, t, g, 0), (m, t, g, 1))
-            const uint32_t m = (uint32_t)(m0 + lane);
-            const U4 w = philox10(U4{m, t, gid, 0u}, T.seed);
-            const U4 v = philox10(U4{m, t, gid, 1u}, T.seed);
+            // With 32 moves per batch the two halves of the wavefront share
+            // each move's work: lanes 0..31 draw its first Philox block and
+            // form the bond (k-1, k), lanes 32..63 the second block and the
+            // bond (k, k+1); a row swap hands each half the other's values.
+            // Same operations on the same operands as one lane doing both.
+            constexpr bool SPLIT = SPLIT_OK && MB == 32;
+            const bool hi = SPLIT && lane >= 32;
+            const uint32_t m = (uint32_t)(m0 + (SPLIT ? (lane & 31) : lane));
+            U4 w, v;
+            if constexpr (SPLIT) {
+                const U4 p = philox10(U4{m, t, gid, hi ? 1u : 0u}, T.seed);
+                const U4 q{other_half(p.x), other_half(p.y), other_half(p.z), other_half(p.w)};
+                w = hi ? q : p;
+                v = hi ? p : q;
+            } else {
+                w = philox10(U4{m, t, gid, 0u}, T.seed);
+                v = philox10(U4{m, t, gid, 1u}, T.seed);
+            }
             MoveRec r;
             r.k = (int)(((uint64_t)w.x * (uint64_t)(uint32_t)n) >> 32);
             r.dx = (unit_open(w.y) - 0.5) * K.edge;
@@ -385,15 +413,27 @@ __device__ __forceinline__ void sweep_moves(const Tables &T, SweepLds<B, W> &S, 
             r.zo = Z[ak];
             const double xn = r.xo + r.dx, yn = r.yo + r.dy, zn = r.zo + r.dz;
             const bool hl = k > 0, hr = k + 1 < n;
-            const int al = G::pos(hl ? k - 1 : k), ar = G::pos(hr ? k + 1 : k);
-            const double xl = X[al], yl = Y[al], zl = Z[al];
-            const double xr = X[ar], yr = Y[ar], zr = Z[ar];
-            const double fln = fene64(K, sq3(xl - xn, yl - yn, zl - zn));
-            const double flo = fene64(K, sq3(xl - r.xo, yl - r.yo, zl - r.zo));
-            const double frn = fene64(K, sq3(xr - xn, yr - yn, zr - zn));
-            const double fro = fene64(K, sq3(xr - r.xo, yr - r.yo, zr - r.zo));
-            r.dfl = hl ? fln - flo : 0.0;
-            r.dfr = hr ? frn - fro : 0.0;
+            if constexpr (SPLIT) {
+                const bool has = hi ? hr : hl;
+                const int ab = G::pos(has ? (hi ? k + 1 : k - 1) : k);
+                const double xb = X[ab], yb = Y[ab], zb = Z[ab];
+                const double fbn = fene64(K, sq3(xb - xn, yb - yn, zb - zn));
+                const double fbo = fene64(K, sq3(xb - r.xo, yb - r.yo, zb - r.zo));
+                const double dfb = has ? fbn - fbo : 0.0;
+                const double dfo = other_half(dfb);
+                r.dfl = hi ? dfo : dfb;
+                r.dfr = hi ? dfb : dfo;
+            } else {
+                const int al = G::pos(hl ? k - 1 : k), ar = G::pos(hr ? k + 1 : k);
+                const double xl = X[al], yl = Y[al], zl = Z[al];
+                const double xr = X[ar], yr = Y[ar], zr = Z[ar];
+                const double fln = fene64(K, sq3(xl - xn, yl - yn, zl - zn));
+                const double flo = fene64(K, sq3(xl - r.xo, yl - r.yo, zl - r.zo));
+                const double frn = fene64(K, sq3(xr - xn, yr - yn, zr - zn));
+                const double fro = fene64(K, sq3(xr - r.xo, yr - r.yo, zr - r.zo));
+                r.dfl = hl ? fln - flo : 0.0;
+                r.dfr = hr ? frn - fro : 0.0;
+            }
             uint64_t cm = 0;
             for (int j = 0; j < MB; ++j) {
                 const int dd = read_lane(k, j) - k;
@@ -1161,7 +1201,10 @@ __device__ __forceinline__ void run_body(const Tables &T, SweepLds<B, W> &S, int
     for (int64_t s = 0; s < n_sweeps; ++s) {
         const int64_t t64 = t0 + s;
         int64_t n_acc = 0, n_rescore = 0;
-        sweep_moves<B, W, MIXED>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
+        // (The four-wavefront persistent kernel keeps the one-lane prologue: with
+        // the split one in its 8-bead body the compiler allocated the 2-bead
+        // body's registers worse, N = 500 x 128 0.425 -> 0.439 ms per sweep.)
+        sweep_moves<B, W, MIXED, (W < 4)>(T, S, rx, ry, rz, g, n, (uint32_t)t64, t64, E, Bd, n_acc, n_rescore);
         sweep_record<B, W>(T, S, g, q, n, t64, E, Bd, n_acc, n_rescore);
         if (!(T.exchange_every > 0 && (t64 + 1) % T.exchange_every == 0)) continue;
         // Publish this conformation at slot g: the block's writes, then (after
