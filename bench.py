@@ -49,6 +49,14 @@ WORKLOADS = {
 }
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries the JSON line alone)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
     import torch
     from paper_1107_3490_amd import pt
@@ -110,10 +118,14 @@ def measured_traffic(workload, kernel, sweeps_per_launch):
         return None
     with open(path) as f:
         t = json.load(f)
-    e = t.get(workload)
-    if e is None or e.get("kernel") != kernel or t.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if t.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    return (e["read_bytes_per_sweep"] + e["write_bytes_per_sweep"]) * sweeps_per_launch
+    e = t.get(workload)
+    entries = e if isinstance(e, list) else [e] if e is not None else []
+    for x in entries:
+        if x.get("kernel") == kernel:
+            return (x["read_bytes_per_sweep"] + x["write_bytes_per_sweep"]) * sweeps_per_launch
+    return None
 
 
 def with_transfers(w, steps):
@@ -330,7 +342,11 @@ def roofline(w, run, steps, workload=None):
     kernel = dominant_kernel(run)
     waves_of_n = {int(m[0]): int(m[2]) for m in run["mapping"]}
     occupied = min(1024, sum(int(r) * waves_of_n[int(n)] for n, r in zip(w.n_beads, w.n_slots)))
-    traffic = measured_traffic(workload, kernel, steps / run["launches"]) if workload else None
+    # A persistent or task-flow launch runs all the timed sweeps of its group
+    # (one launch per group); a per-sweep launch one sweep.
+    b_, w_ = max(run["classes"], key=lambda c: c[0] * c[1])
+    per_launch = steps if run["class_mode"][(b_, w_)] in (1, 2) else steps / run["launches"]
+    traffic = measured_traffic(workload, kernel, per_launch) if workload else None
     return {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 FETCH_SIZE/WRITE_SIZE x copy calibration)",
@@ -345,7 +361,9 @@ def sub_record(name, steps, warmup, cpu_budget_s, with_cpu, cpu_chains=None):
     from paper_1107_3490_amd import inputs as I
 
     w = I.named(name)
+    progress(f"{name}: mixed")
     mixed = run_gpu(w, "mixed", steps, warmup)
+    progress(f"{name}: fp64")
     fp64 = run_gpu(w, "fp64", steps, warmup)
     pps = w.pair_interactions_per_sweep()
     rec = {"workload": f"{name}: {WORKLOADS[name]}", "steps": steps, "warmup": warmup,
@@ -364,6 +382,7 @@ def sub_record(name, steps, warmup, cpu_budget_s, with_cpu, cpu_chains=None):
                     "launches": fp64["launches"]}}
     rec["mixed_over_fp64"] = rec["mixed"]["value"] / rec["fp64"]["value"]
     if with_cpu:
+        progress(f"{name}: CPU oracle")
         ws = I.subset(w, cpu_chains) if cpu_chains is not None else w
         cb = cpu_baseline(ws, budget_s=cpu_budget_s)
         if cpu_chains is not None:
@@ -420,7 +439,9 @@ def main():
     from paper_1107_3490_amd import inputs as I
 
     w = I.named(args.workload)
+    progress(f"{args.workload}: mixed")
     mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.schedule, not args.no_tune)
+    progress(f"{args.workload}: fp64")
     fp64 = run_gpu(w, "fp64", args.steps, args.warmup, args.schedule, not args.no_tune)
 
     slots = w.total_slots
@@ -473,6 +494,7 @@ def main():
     # The mixed path with every accepted move also re-scored in the FP64 order:
     # same decisions, running energies within 1e-9 like the FP64 path's.
     from paper_1107_3490_amd import pt as _pt
+    progress(f"{args.workload}: mixed, FP64 re-score of accepted moves")
     acc64 = run_gpu(w, "mixed", args.steps, args.warmup, args.schedule | _pt.PT_SCHED_FP64_ON_ACCEPT,
                     not args.no_tune)
     acc64_value = acc64["pairs"] / (acc64["event_total_ms"] / 1e3)
@@ -482,6 +504,7 @@ def main():
                                    "mapping_N_B_W": acc64["mapping"]}
     out["incl_init_and_readback"] = with_transfers(w, args.steps)
     if not args.no_cpu:
+        progress(f"{args.workload}: CPU oracle")
         out["cpu_baseline"] = cpu_baseline(w)
         # one core, the convention of the paper's speed-ups (context only)
         out["cpu_baseline_1core"] = cpu_baseline(w, budget_s=5.0, threads=1)
