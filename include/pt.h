@@ -47,7 +47,7 @@
  * its running energies carry that bound and are re-synchronised with the FP64
  * energy whenever an exchange decision needs it.  At the end of a sweep the running
  * energy is replaced by the FP64-order energy when its bound exceeds 2^-30
- * (PT_FP64, and PT_MIXED with PT_SCHED_FP64_ON_ACCEPT) or 2^-10 (PT_MIXED)
+ * (PT_FP64, and PT_MIXED with PT_SCHED_FP64_ON_ACCEPT) or 2^-6 (PT_MIXED)
  * of max(1, |E|).
  *
  * Threading: a handle is not thread-safe.  Separate handles on separate
