@@ -211,6 +211,7 @@ def paper_protocol(n_beads=55, sweeps=4000, every=1000, edge=0.02,
     for nr in replicas:
         w = workload(nr)
         for prec in ("mixed", "fp64"):
+            progress(f"paper protocol: n_r = {nr}, {prec}")
             code = int(pt.autotune(w, prec, trial_sweeps=20)[0])
             t_gpu = t_run(w, prec, [code])
             t_default = t_run(w, prec, None)
@@ -257,6 +258,7 @@ def ablations(sweeps=40, warmup=5):
 
     lane_rows = []
     for nr in (64, 256, 1024, 4096, 16384):
+        progress(f"ablations: one lane per replica, n_r = {nr}")
         w = chain55(nr)
         wave_ms, pers = timed(w, "fp64")
         lane_ms, _ = timed(w, "fp64", mapping=[pt.PT_MAP_LANE | 0x11])
@@ -267,6 +269,7 @@ def ablations(sweeps=40, warmup=5):
     energy_rows = []
     for name, w in (("c2", I.named("c2")), ("c3", I.named("c3")), ("N=55 x 4096", chain55(4096))):
         for prec in ("mixed", "fp64"):
+            progress(f"ablations: full energy every sweep, {name}, {prec}")
             run_ms, pers = timed(w, prec)
             full_ms, _ = timed(w, prec, schedule=pt.PT_SCHED_FULL_ENERGY)
             energy_rows.append({"workload": name, "precision": prec, "persistent": pers,
