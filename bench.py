@@ -57,12 +57,16 @@ def progress(msg):
     print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(w, precision, steps, warmup, schedule=0, tune=True):
+def run_gpu(w, precision, steps, warmup, schedule=0, tune=True, by_n=None):
     import torch
     from paper_1107_3490_amd import pt
 
-    # The mapping autotuner (outside the timed region); results do not depend on it.
-    mapping = pt.autotune(w, precision, schedule, trial_sweeps=20) if tune else None
+    # The mapping autotuner (outside the timed region), or the caller's mapping
+    # per chain length (by_n); results do not depend on it.
+    if by_n is not None:
+        mapping = np.array([by_n[int(n)] for n in w.n_beads], dtype=np.int32)
+    else:
+        mapping = pt.autotune(w, precision, schedule, trial_sweeps=20) if tune else None
     sim = pt.Simulation(w, precision=precision, schedule=schedule, mapping=mapping)
     bpl, wpr, _ = sim.mapping()
     codes = list(mapping) if mapping is not None else [0] * len(w.n_beads)
@@ -409,6 +413,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2, 3],
                     help="0 auto, 1 one sweep launch per sweep, 2 persistent, 3 task flow")
     ap.add_argument("--no-tune", action="store_true", help="default mapping instead of the autotuner's")
+    ap.add_argument("--mapping", default=None,
+                    help="mapping per chain length instead of the autotuner's, e.g. "
+                         "'13:0x11,30:0x11,55:0x11,100:0x21,200:0x14,500:0x24' (code 16 B + W)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--paper-protocol", action="store_true",
@@ -442,10 +449,17 @@ def main():
     from paper_1107_3490_amd import inputs as I
 
     w = I.named(args.workload)
+    by_n = None
+    if args.mapping:
+        by_n = {int(n): int(c, 0) for n, c in (x.split(":") for x in args.mapping.split(","))}
+        missing = sorted(set(int(n) for n in w.n_beads) - set(by_n))
+        if missing:
+            print(f"--mapping has no code for chain length(s) {missing}", file=sys.stderr)
+            sys.exit(2)
     progress(f"{args.workload}: mixed")
-    mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.schedule, not args.no_tune)
+    mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.schedule, not args.no_tune, by_n)
     progress(f"{args.workload}: fp64")
-    fp64 = run_gpu(w, "fp64", args.steps, args.warmup, args.schedule, not args.no_tune)
+    fp64 = run_gpu(w, "fp64", args.steps, args.warmup, args.schedule, not args.no_tune, by_n)
 
     slots = w.total_slots
     value = mixed["pairs"] / (mixed["event_total_ms"] / 1e3)
@@ -499,7 +513,7 @@ def main():
     from paper_1107_3490_amd import pt as _pt
     progress(f"{args.workload}: mixed, FP64 re-score of accepted moves")
     acc64 = run_gpu(w, "mixed", args.steps, args.warmup, args.schedule | _pt.PT_SCHED_FP64_ON_ACCEPT,
-                    not args.no_tune)
+                    not args.no_tune, by_n)
     acc64_value = acc64["pairs"] / (acc64["event_total_ms"] / 1e3)
     out["mixed_fp64_on_accept"] = {"value": acc64_value, "unit": "pair interactions/s",
                                    "ms_per_step": acc64["event_total_ms"] / args.steps,
