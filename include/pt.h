@@ -253,8 +253,9 @@ PT_API int pt_get_logs(pt_handle *h, uint64_t *h_accept_log, int64_t *accept_row
  * also packed two and four replicas per wavefront (PT_MAP_PACK2, PT_MAP_PACK4),
  * and, for PT_FP64, one lane per replica (PT_MAP_LANE) -- on the batch's chains
  * of that length
- * (their own slots, ladders, coordinates, precision and schedule), the fastest
- * of three timings of trial_sweeps sweeps after a warm-up, in a device
+ * (their own slots, ladders, coordinates, precision and schedule) over
+ * trial_sweeps sweeps after a warm-up (a candidate within 3% of the best so
+ * far is timed twice more and its fastest timing kept), in a device
  * workspace of its own on
  * hip_stream, and writes the fastest code to mapping_out[n_chains] (ready for
  * config.mapping).  Unless the schedule is PT_SCHED_PER_SWEEP it then times
