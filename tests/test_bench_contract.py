@@ -19,5 +19,16 @@ def test_options_are_documented():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    for opt in ("--gpus", "--steps", "--warmup", "--workload", "--schedule", "--paper-protocol", "--ablations"):
+    for opt in ("--gpus", "--steps", "--warmup", "--workload", "--schedule", "--mapping", "--paper-protocol",
+                "--ablations"):
         assert opt in r.stdout
+
+
+def test_mapping_must_cover_every_chain_length():
+    # the default workload is one chain of N = 100: a mapping for N = 55 only is refused
+    # before any device work
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mapping", "55:0x11", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "no code for chain length(s) [100]" in r.stderr
+    assert r.stdout.strip() == ""
